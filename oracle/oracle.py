@@ -1,0 +1,216 @@
+"""ctypes wrapper of the C oracle (test infrastructure only).
+
+Every function takes and returns NumPy arrays.  Semantics follow the paper's
+section 2 (HOP) and section 3.1 (per-task rules); the C source states the
+readings taken where the paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+__all__ = [
+    "lib", "knn", "density", "norm", "hop", "chains", "saddles", "merge", "labels",
+    "run", "OracleResult", "num_threads", "HopParams",
+]
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        L = C.CDLL(path)
+        i64, i32, f64, vp = C.c_int64, C.c_int, C.c_double, C.c_void_p
+        L.orc_knn_brute.argtypes = [i64, vp, vp, i32, i32, i32, vp, i64, vp, vp]
+        L.orc_knn_kdtree.argtypes = [i64, vp, vp, i32, i32, i32, vp, i64, vp, vp]
+        L.orc_density.argtypes = [i64, i32, vp, f64, vp]
+        L.orc_norm.argtypes = [f64]
+        L.orc_norm.restype = f64
+        L.orc_hop.argtypes = [i64, i32, i32, vp, vp, vp, vp, i32, vp]
+        L.orc_chains.argtypes = [i64, vp, vp, vp, f64, vp, vp, vp, vp, vp]
+        L.orc_saddles.argtypes = [i64, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp, i64, vp]
+        L.orc_merge.argtypes = [i64, vp, i64, vp, vp, vp, f64, f64, vp]
+        L.orc_labels.argtypes = [i64, vp, i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
+        L.orc_run.argtypes = [i64, vp, vp, vp, i32, i32, i32, i32, i32, i32, f64, f64, f64, f64,
+                              i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_num_threads.restype = i32
+        _LIB = L
+    return _LIB
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+@dataclass
+class HopParams:
+    """HOP parameters (section 4.1 and Table 2 of the paper)."""
+    n_dens: int = 64
+    n_hop: int = 16
+    n_merge: int = 4
+    k_store: int = 64
+    delta_outer: float = 80.0
+    delta_saddle: float = 200.0
+    delta_peak: float = 240.0
+    grid_bits: int = 21
+
+
+def knn(pos, k, periodic=True, ids=None, queries=None, method="kdtree", grid_bits=21):
+    """Neighbour lists (self first, then by (d^2, id, index)) and their d^2."""
+    pos = _c(pos, np.uint32)
+    n = pos.shape[0]
+    q = _c(queries, np.int64)
+    nq = n if q is None else q.shape[0]
+    nbr = np.empty((nq, k), np.int32)
+    d2 = np.empty((nq, k), np.int64)
+    f = lib().orc_knn_kdtree if method == "kdtree" else lib().orc_knn_brute
+    _check(f(n, _p(pos), _p(_c(ids, np.int64)), int(periodic), grid_bits, k, _p(q), nq,
+             _p(nbr), _p(d2)), "knn")
+    return nbr, d2
+
+
+def norm(mean_density: float) -> float:
+    return float(lib().orc_norm(mean_density))
+
+
+def density(d2, mean_density):
+    d2 = _c(d2, np.int64)
+    nq, k = d2.shape
+    out = np.empty(nq, np.float64)
+    _check(lib().orc_density(nq, k, _p(d2), float(mean_density), _p(out)), "density")
+    return out
+
+
+def hop(nbr, dens, n_hop, ids=None, padded=None, padded_rules=False):
+    nbr = _c(nbr, np.int32)
+    n, ks = nbr.shape
+    out = np.empty(n, np.int32)
+    _check(lib().orc_hop(n, ks, n_hop, _p(nbr), _p(_c(dens, np.float64)), _p(_c(ids, np.int64)),
+                         _p(_c(padded, np.uint8)), int(padded_rules), _p(out)), "hop")
+    return out
+
+
+def chains(hop_, dens, delta_outer, ids=None):
+    hop_ = _c(hop_, np.int32)
+    n = hop_.shape[0]
+    root = np.empty(n, np.int32)
+    chain_of = np.empty(n, np.int32)
+    croot = np.empty(max(n, 1), np.int32)
+    cpeak = np.empty(max(n, 1), np.float64)
+    nc = np.zeros(1, np.int64)
+    _check(lib().orc_chains(n, _p(hop_), _p(_c(dens, np.float64)), _p(_c(ids, np.int64)),
+                            float(delta_outer), _p(root), _p(chain_of), _p(croot), _p(cpeak),
+                            _p(nc)), "chains")
+    c = int(nc[0])
+    return root, chain_of, croot[:c].copy(), cpeak[:c].copy()
+
+
+def saddles(nbr, dens, chain_of, n_merge, padded=None, padded_rules=False):
+    nbr = _c(nbr, np.int32)
+    n, ks = nbr.shape
+    cap = n * max(n_merge - 1, 1) + 1
+    lo = np.empty(cap, np.int32)
+    hi = np.empty(cap, np.int32)
+    s = np.empty(cap, np.float64)
+    ne = np.zeros(1, np.int64)
+    _check(lib().orc_saddles(n, ks, n_merge, _p(nbr), _p(_c(dens, np.float64)),
+                             _p(_c(chain_of, np.int32)), _p(_c(padded, np.uint8)),
+                             int(padded_rules), _p(lo), _p(hi), _p(s), cap, _p(ne)), "saddles")
+    e = int(ne[0])
+    return lo[:e].copy(), hi[:e].copy(), s[:e].copy()
+
+
+def merge(chain_peak, e_lo, e_hi, e_s, delta_saddle, delta_peak):
+    cp = _c(chain_peak, np.float64)
+    nc = cp.shape[0]
+    out = np.empty(max(nc, 1), np.int32)
+    e_lo, e_hi, e_s = _c(e_lo, np.int32), _c(e_hi, np.int32), _c(e_s, np.float64)
+    _check(lib().orc_merge(nc, _p(cp), e_lo.shape[0], _p(e_lo), _p(e_hi), _p(e_s),
+                           float(delta_saddle), float(delta_peak), _p(out)), "merge")
+    return out[:nc].copy()
+
+
+def labels(chain_of, chain_root, chain_peak, chain_halo, ids=None, padded=None,
+           padded_rules=False):
+    chain_of = _c(chain_of, np.int32)
+    n = chain_of.shape[0]
+    nc = len(chain_root)
+    group = np.empty(n, np.int32)
+    ng = np.zeros(1, np.int64)
+    cap = max(nc, 1)
+    gc = np.empty(cap, np.int64)
+    gp = np.empty(cap, np.int32)
+    gd = np.empty(cap, np.float64)
+    _check(lib().orc_labels(n, _p(chain_of), nc, _p(_c(chain_root, np.int32)),
+                            _p(_c(chain_peak, np.float64)), _p(_c(chain_halo, np.int32)),
+                            _p(_c(ids, np.int64)), _p(_c(padded, np.uint8)), int(padded_rules),
+                            _p(group), _p(ng), _p(gc), _p(gp), _p(gd)), "labels")
+    g = int(ng[0])
+    return group, gc[:g].copy(), gp[:g].copy(), gd[:g].copy()
+
+
+@dataclass
+class OracleResult:
+    density: np.ndarray
+    nbr: np.ndarray
+    hop: np.ndarray
+    root: np.ndarray
+    chain_of: np.ndarray
+    group: np.ndarray
+    g_count: np.ndarray
+    g_peak: np.ndarray
+    g_peak_dens: np.ndarray
+    n_chains: int
+    n_edges: int
+    n_groups: int
+
+
+def run(pos, periodic=True, mean_density=None, params: HopParams | None = None, ids=None,
+        padded=None, padded_rules=False, search="kdtree") -> OracleResult:
+    """The whole pipeline: density, links, chains, boundaries, merge, labels."""
+    p = params or HopParams()
+    pos = _c(pos, np.uint32)
+    n = pos.shape[0]
+    if mean_density is None:
+        mean_density = n / float(1 << (3 * p.grid_bits))
+    dens = np.empty(n, np.float64)
+    nbr = np.empty((n, p.k_store), np.int32)
+    hop_ = np.empty(n, np.int32)
+    root = np.empty(n, np.int32)
+    chain_of = np.empty(n, np.int32)
+    group = np.empty(n, np.int32)
+    gc = np.empty(max(n, 1), np.int64)
+    gp = np.empty(max(n, 1), np.int32)
+    gd = np.empty(max(n, 1), np.float64)
+    counts = np.zeros(3, np.int64)
+    _check(lib().orc_run(n, _p(pos), _p(_c(ids, np.int64)), _p(_c(padded, np.uint8)),
+                         int(periodic), p.grid_bits, p.n_dens, p.n_hop, p.n_merge, p.k_store,
+                         p.delta_outer, p.delta_saddle, p.delta_peak, float(mean_density),
+                         int(padded_rules), 1 if search == "kdtree" else 0,
+                         _p(dens), _p(nbr), _p(hop_), _p(root), _p(chain_of), _p(group),
+                         _p(gc), _p(gp), _p(gd), _p(counts)), "run")
+    g = int(counts[2])
+    return OracleResult(dens, nbr, hop_, root, chain_of, group, gc[:g].copy(), gp[:g].copy(),
+                        gd[:g].copy(), int(counts[0]), int(counts[1]), g)
