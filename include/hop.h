@@ -1,0 +1,226 @@
+/*
+ * hop.h -- C ABI of the MI355X HOP hot path.
+ *
+ * HOP (Eisenstein & Hut 1998) as described in Skory et al., "Parallel HOP",
+ * section 2, run on one GPU for either a whole periodic box or one task's
+ * padded subvolume (section 3.1).  The stages are:
+ *
+ *   hop_density  kNN (N_dens nearest, self included) + SPH density  (sec. 2, stage 1)
+ *   hop_link     link to the densest of the N_hop nearest            (sec. 2, stage 2)
+ *   hop_groups   chains to self-linked peaks, delta_outer cut        (sec. 2, stage 3; merge step 1)
+ *   hop_merge    boundary table, proto-halo and sub-peak merge,
+ *                group labels                                        (sec. 2, merge steps 2-5;
+ *                                                                     sec. 3.1 last step)
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - All array arguments are DEVICE pointers allocated and owned by the
+ *   caller; the library never frees them.  Arrays are indexed by the
+ *   caller's particle order ("input order"); neighbour, link, root and peak
+ *   values are input-order indices.  The library's internal particle order
+ *   never appears in an output.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *   work and return without waiting, except where a host-side count is
+ *   returned (hop_groups, hop_merge): those synchronise `stream` first.
+ * - Returns HOP_OK (0) or a negative HOP_ERR_* code; hop_last_error()
+ *   gives a message.  Nothing is thrown across the ABI.  On error the
+ *   outputs are unspecified but nothing is written out of bounds.
+ * - Errors found on the device (coordinate out of range, degenerate
+ *   neighbourhood, bad index in an input array) are reported by the next
+ *   call that synchronises, at the latest.
+ * - A context is not thread-safe; use one context per host thread.
+ *   Calls made through one context use its scratch memory, so two calls
+ *   on one context must not overlap on different streams.
+ * - Particle counts: n_dens <= n < 2^31.
+ */
+#ifndef HOP_H
+#define HOP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define HOP_OK              0
+#define HOP_ERR_ARG        (-1) /* bad argument (NULL, size, parameter range)            */
+#define HOP_ERR_RANGE      (-2) /* coordinate >= 2^grid_bits, or index out of [0,n)       */
+#define HOP_ERR_DEGENERATE (-3) /* r_max = 0: at least n_dens coincident particles        */
+#define HOP_ERR_CAPACITY   (-4) /* an internal table could not hold the input             */
+#define HOP_ERR_NOMEM      (-5) /* device allocation failed                               */
+#define HOP_ERR_HIP        (-6) /* a HIP runtime call failed                              */
+
+/* hop_params.flags */
+#define HOP_PERIODIC       0x1u /* whole periodic box: minimum-image distances            */
+#define HOP_DENSITY_FP32   0x2u /* FP32 density arithmetic (the FP64 path is the default) */
+#define HOP_PADDED_RULES   0x4u /* section 3.1 rules for padded particles                 */
+
+/*
+ * Parameters (section 4.1 and Table 2 of the paper).  Constraints:
+ *   1 <= n_merge <= n_hop <= k_store <= n_dens <= 64,
+ *   delta_* finite and >= 0, mean_density > 0 (or 0 for the default),
+ *   1 <= grid_bits <= 21.
+ * n_dens     particles in the smoothing kernel, self included
+ * n_hop      neighbours searched for the densest link, self included
+ * n_merge    neighbours searched for chain boundaries, self included
+ * k_store    neighbour-list columns written by hop_density
+ * delta_outer / delta_saddle / delta_peak   thresholds in units of the mean
+ *            density (paper defaults 80 / 2.5*80 / 3*80)
+ * mean_density  particles per grid-unit^3 used to normalise the density;
+ *            0 selects n / 2^(3*grid_bits), the whole-box value.  For a
+ *            subvolume pass the global value (section 2: normalised to the
+ *            mean density of the simulation volume).
+ * grid_bits  coordinates are integers in [0, 2^grid_bits)
+ */
+typedef struct hop_params {
+    int32_t n_dens;
+    int32_t n_hop;
+    int32_t n_merge;
+    int32_t k_store;
+    double delta_outer;
+    double delta_saddle;
+    double delta_peak;
+    double mean_density;
+    uint32_t grid_bits;
+    uint32_t flags;
+} hop_params;
+
+/* one output group (halo); groups are numbered by count descending, then
+   peak density descending, then peak index ascending */
+typedef struct hop_group_info {
+    int64_t count;        /* particles carrying this label                   */
+    int32_t peak;         /* input index of the densest particle              */
+    int32_t reserved;
+    double peak_density;  /* its density                                      */
+} hop_group_info;
+
+typedef struct hop_ctx hop_ctx;
+
+/* Fills the defaults: 64/16/4/64, 80/200/240, mean_density 0, 21 bits,
+   HOP_PERIODIC. */
+void hop_params_default(hop_params *p);
+
+/* Creates a context on HIP device `device`.  The context owns the scratch
+   memory (sorted particle copy, search tree, hash tables); it grows on
+   demand and is released by hop_ctx_destroy. */
+int hop_ctx_create(int device, hop_ctx **out);
+void hop_ctx_destroy(hop_ctx *ctx);
+
+/* Message describing the last error on this context ("" if none).  The
+   pointer stays valid until the next call on the context. */
+const char *hop_last_error(const hop_ctx *ctx);
+
+/*
+ * hop_density -- neighbour lists and SPH densities (section 2, stage 1).
+ *
+ * For every particle i: L_i = [i, then the n_dens-1 nearest others ordered
+ * by (squared distance, id)], with minimum-image distances under
+ * HOP_PERIODIC, plain differences otherwise.  Distances are exact integers.
+ * r_max^2 = d^2 to L_i[n_dens-1], h = r_max/2, and
+ *   density[i] = sum_t W(|x_i - x_{L_i[t]}|, h) / mean_density
+ * with the M4 cubic spline W (unit masses), summed pairwise over a
+ * zero-padded 64-slot array.
+ *
+ * n        particle count
+ * pos      [n][3] uint32 coordinates, each < 2^grid_bits (else HOP_ERR_RANGE)
+ * id       [n] int64 tie-break ids, or NULL to break ties by index.  Must be
+ *          distinct when given.
+ * density  [n] output, FP64
+ * nbr      [n][k_store] output: the first k_store entries of L_i, or NULL
+ * Errors: HOP_ERR_DEGENERATE when some r_max is 0.
+ */
+int hop_density(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
+                const hop_params *p, double *density, int32_t *nbr, void *stream);
+
+/*
+ * hop_link -- densest-neighbour links (section 2, stage 2).
+ *
+ * hop[i] = the particle j among nbr[i][0 .. n_hop) (self included) with the
+ * largest density; equal densities go to the smaller id (index when id is
+ * NULL).  Under HOP_PADDED_RULES a padded particle links to itself
+ * (section 3.1: no chain link from a padded particle).
+ *
+ * nbr      [n][k_store] as written by hop_density (k_store from p)
+ * density  [n]
+ * id       [n] or NULL, as given to hop_density
+ * padded   [n] uint8 (nonzero = padded) or NULL
+ * hop      [n] output
+ */
+int hop_link(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
+             const int64_t *id, const uint8_t *padded, const hop_params *p, int32_t *hop,
+             void *stream);
+
+/*
+ * hop_groups -- chains (section 2, stage 3 and merge step 1).
+ *
+ * root[i] = the self-linked particle reached by following hop from i.
+ * Particles with density < delta_outer are excluded.  Chains are the roots
+ * of the remaining particles, numbered 0..n_chains-1 by the root's id
+ * (index when id is NULL); chain_of[i] is that number, -1 when excluded.
+ *
+ * hop       [n] from hop_link
+ * density   [n]
+ * id        [n] or NULL
+ * root      [n] output
+ * chain_of  [n] output
+ * n_chains  HOST pointer, output.  Synchronises `stream`.
+ */
+int hop_groups(hop_ctx *ctx, int64_t n, const int32_t *hop, const double *density,
+               const int64_t *id, const hop_params *p, int32_t *root, int32_t *chain_of,
+               int32_t *n_chains, void *stream);
+
+/*
+ * hop_merge -- chain boundaries, merge and labels (section 2, merge steps
+ * 2-5; section 3.1, boundary and output rules).
+ *
+ * Boundaries: for every chained particle i and j among nbr[i][1 .. n_merge)
+ * in a different chain (and, under HOP_PADDED_RULES, not both padded),
+ * delta_link = 0.5*(density[i] + density[j]); each chain pair keeps its
+ * maximum.  Chains whose peak density >= delta_peak are proto-halos;
+ * proto-halos sharing a boundary >= delta_saddle merge; every other chain
+ * joins the halo reached through its densest chain of boundaries (the
+ * maximum spanning forest of the chain graph with the proto-halos tied to
+ * one virtual root; boundaries ordered by delta_link, then chain numbers).
+ * Chains that reach no proto-halo are dropped.
+ *
+ * group[i] = the halo number of particle i, or -1 (excluded, dropped, or
+ * padded under HOP_PADDED_RULES).  Halos are numbered by particle count
+ * descending, then peak density descending, then peak id ascending; a halo
+ * with no labelled particle gets no number.
+ *
+ * nbr, density, id, padded   as for hop_link
+ * root, chain_of, n_chains   from hop_groups
+ * group     [n] output
+ * n_groups  HOST pointer, output.  Synchronises `stream`.
+ * groups    [n_chains] device output table, or NULL; entries 0..n_groups-1
+ *           are written
+ */
+int hop_merge(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
+              const int32_t *root, const int32_t *chain_of, int32_t n_chains, const int64_t *id,
+              const uint8_t *padded, const hop_params *p, int32_t *group, int32_t *n_groups,
+              hop_group_info *groups, void *stream);
+
+/* Synchronises `stream` and reports any error the device recorded since the
+   last synchronising call (see the conventions above). */
+int hop_sync(hop_ctx *ctx, void *stream);
+
+/* Per-call statistics of the last hop_density on this context. */
+typedef struct hop_stats {
+    double ms_sort;         /* Morton sort + tree build                          */
+    double ms_knn;          /* kNN + density kernel                              */
+    int64_t n;              /* particles                                          */
+    int64_t nodes_visited;  /* tree nodes tested, summed over waves (0 if off)   */
+    int64_t leaves_scanned; /* leaves whose points were tested                   */
+} hop_stats;
+
+/* Turns device-side counters and per-stage timing on or off (default off);
+   timing synchronises the stream inside hop_density. */
+int hop_set_profiling(hop_ctx *ctx, int on);
+int hop_get_stats(const hop_ctx *ctx, hop_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOP_H */

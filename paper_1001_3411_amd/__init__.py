@@ -1,0 +1,259 @@
+"""MI355X HOP hot path: Python binding of the C ABI in include/hop.h.
+
+The binding only marshals arguments: every stage runs in the HIP kernels of
+libhop.so.  PyTorch supplies device memory and the current stream.  Loading
+fails loudly when the library has not been built (run
+``__graft_entry__.build()`` or ``python paper_1001_3411_amd/build.py``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+__all__ = [
+    "LIB_PATH", "load", "HopParams", "HopError", "HopContext", "HOP_PERIODIC",
+    "HOP_DENSITY_FP32", "HOP_PADDED_RULES", "exported_symbols",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhop.so")
+
+HOP_PERIODIC = 0x1
+HOP_DENSITY_FP32 = 0x2
+HOP_PADDED_RULES = 0x4
+
+ERRORS = {-1: "HOP_ERR_ARG", -2: "HOP_ERR_RANGE", -3: "HOP_ERR_DEGENERATE",
+          -4: "HOP_ERR_CAPACITY", -5: "HOP_ERR_NOMEM", -6: "HOP_ERR_HIP"}
+
+
+class HopError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Params(C.Structure):
+    _fields_ = [("n_dens", C.c_int32), ("n_hop", C.c_int32), ("n_merge", C.c_int32),
+                ("k_store", C.c_int32), ("delta_outer", C.c_double),
+                ("delta_saddle", C.c_double), ("delta_peak", C.c_double),
+                ("mean_density", C.c_double), ("grid_bits", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class _GroupInfo(C.Structure):
+    _fields_ = [("count", C.c_int64), ("peak", C.c_int32), ("reserved", C.c_int32),
+                ("peak_density", C.c_double)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("ms_sort", C.c_double), ("ms_knn", C.c_double), ("n", C.c_int64),
+                ("nodes_visited", C.c_int64), ("leaves_scanned", C.c_int64)]
+
+
+@dataclass
+class HopParams:
+    """Section 4.1 / Table 2 parameters; defaults are the paper's thresholds
+    (80, 2.5x, 3x) with N_dens = 64, N_hop = 16, N_merge = 4."""
+    n_dens: int = 64
+    n_hop: int = 16
+    n_merge: int = 4
+    k_store: int = 64
+    delta_outer: float = 80.0
+    delta_saddle: float = 200.0
+    delta_peak: float = 240.0
+    mean_density: float = 0.0
+    grid_bits: int = 21
+    periodic: bool = True
+    padded_rules: bool = False
+    density_fp32: bool = False
+
+    def c(self) -> _Params:
+        flags = (HOP_PERIODIC if self.periodic else 0) | \
+                (HOP_PADDED_RULES if self.padded_rules else 0) | \
+                (HOP_DENSITY_FP32 if self.density_fp32 else 0)
+        return _Params(self.n_dens, self.n_hop, self.n_merge, self.k_store, self.delta_outer,
+                       self.delta_saddle, self.delta_peak, self.mean_density, self.grid_bits,
+                       flags)
+
+
+_LIB = None
+
+
+def load():
+    """Load libhop.so; raises if it is missing (there is no fallback path)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+    L.hop_params_default.argtypes = [C.POINTER(_Params)]
+    L.hop_params_default.restype = None
+    L.hop_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+    L.hop_ctx_destroy.argtypes = [vp]
+    L.hop_ctx_destroy.restype = None
+    L.hop_last_error.argtypes = [vp]
+    L.hop_last_error.restype = C.c_char_p
+    L.hop_density.argtypes = [vp, i64, vp, vp, C.POINTER(_Params), vp, vp, vp]
+    L.hop_link.argtypes = [vp, i64, vp, vp, vp, vp, C.POINTER(_Params), vp, vp]
+    L.hop_groups.argtypes = [vp, i64, vp, vp, vp, C.POINTER(_Params), vp, vp,
+                             C.POINTER(i32), vp]
+    L.hop_merge.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, C.POINTER(_Params), vp,
+                            C.POINTER(i32), vp, vp]
+    L.hop_sync.argtypes = [vp, vp]
+    L.hop_set_profiling.argtypes = [vp, C.c_int]
+    L.hop_get_stats.argtypes = [vp, C.POINTER(_Stats)]
+    _LIB = L
+    return L
+
+
+def exported_symbols():
+    """Names of the C functions declared in include/hop.h."""
+    import re
+    hdr = os.path.join(os.path.dirname(HERE), "include", "hop.h")
+    with open(hdr) as f:
+        txt = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?(hop_\w+)\s*\(", txt, re.M)))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class HopContext:
+    """One library context on one device (scratch memory lives here)."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        self.device = device
+        h = C.c_void_p()
+        rc = self.lib.hop_ctx_create(device, C.byref(h))
+        if rc != 0:
+            raise HopError(rc, "hop_ctx_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hop_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ------------------------------------------------------------
+    def _check(self, rc):
+        if rc != 0:
+            raise HopError(rc, self.lib.hop_last_error(self.h).decode())
+
+    def _stream(self, stream):
+        if stream is None:
+            stream = self._torch.cuda.current_stream(self.device)
+        return C.c_void_p(stream.cuda_stream)
+
+    def _dev(self, t, dtype):
+        torch = self._torch
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor):
+            import numpy as np
+            a = np.ascontiguousarray(t)
+            if a.dtype == np.uint32:
+                a = a.view(np.int32)  # same bits; the ABI reads uint32
+            t = torch.from_numpy(a)
+        return t.to(device=f"cuda:{self.device}", dtype=dtype).contiguous()
+
+    # -- stages -------------------------------------------------------------
+    def density(self, pos, params: HopParams | None = None, ids=None, want_nbr=True,
+                stream=None):
+        torch = self._torch
+        p = params or HopParams()
+        pos = self._dev(pos, torch.int32).view(torch.int32)
+        n = pos.shape[0]
+        ids = self._dev(ids, torch.int64)
+        dens = torch.empty(n, dtype=torch.float64, device=pos.device)
+        nbr = torch.empty((n, p.k_store), dtype=torch.int32, device=pos.device) if want_nbr else None
+        cp = p.c()
+        self._check(self.lib.hop_density(self.h, n, _ptr(pos), _ptr(ids), C.byref(cp), _ptr(dens),
+                                         _ptr(nbr), self._stream(stream)))
+        return dens, nbr
+
+    def link(self, nbr, dens, params: HopParams | None = None, ids=None, padded=None,
+             stream=None):
+        torch = self._torch
+        p = params or HopParams()
+        n = nbr.shape[0]
+        hop = torch.empty(n, dtype=torch.int32, device=nbr.device)
+        cp = p.c()
+        self._check(self.lib.hop_link(self.h, n, _ptr(nbr), _ptr(dens),
+                                      _ptr(self._dev(ids, torch.int64)),
+                                      _ptr(self._dev(padded, torch.uint8)), C.byref(cp),
+                                      _ptr(hop), self._stream(stream)))
+        return hop
+
+    def groups(self, hop, dens, params: HopParams | None = None, ids=None, stream=None):
+        torch = self._torch
+        p = params or HopParams()
+        n = hop.shape[0]
+        root = torch.empty(n, dtype=torch.int32, device=hop.device)
+        chain_of = torch.empty(n, dtype=torch.int32, device=hop.device)
+        nc = C.c_int32(0)
+        cp = p.c()
+        self._check(self.lib.hop_groups(self.h, n, _ptr(hop), _ptr(dens),
+                                        _ptr(self._dev(ids, torch.int64)), C.byref(cp),
+                                        _ptr(root), _ptr(chain_of), C.byref(nc),
+                                        self._stream(stream)))
+        return root, chain_of, int(nc.value)
+
+    def merge(self, nbr, dens, root, chain_of, n_chains, params: HopParams | None = None,
+              ids=None, padded=None, want_table=True, stream=None):
+        torch = self._torch
+        p = params or HopParams()
+        n = nbr.shape[0]
+        group = torch.empty(n, dtype=torch.int32, device=nbr.device)
+        table = None
+        if want_table:
+            table = torch.empty((max(n_chains, 1), 3), dtype=torch.int64, device=nbr.device)
+        ng = C.c_int32(0)
+        cp = p.c()
+        self._check(self.lib.hop_merge(self.h, n, _ptr(nbr), _ptr(dens), _ptr(root),
+                                       _ptr(chain_of), n_chains,
+                                       _ptr(self._dev(ids, torch.int64)),
+                                       _ptr(self._dev(padded, torch.uint8)), C.byref(cp),
+                                       _ptr(group), C.byref(ng), _ptr(table),
+                                       self._stream(stream)))
+        g = int(ng.value)
+        out = {"group": group, "n_groups": g}
+        if want_table:
+            t = table[:g]
+            out["g_count"] = t[:, 0].clone()
+            out["g_peak"] = (t[:, 1] & 0xFFFFFFFF).to(torch.int32)
+            out["g_peak_dens"] = t[:, 2].contiguous().view(torch.float64)
+        return out
+
+    def sync(self, stream=None):
+        self._check(self.lib.hop_sync(self.h, self._stream(stream)))
+
+    def run(self, pos, params: HopParams | None = None, ids=None, padded=None, stream=None):
+        """All four stages; returns a dict of device tensors."""
+        p = params or HopParams()
+        dens, nbr = self.density(pos, p, ids=ids, stream=stream)
+        hop = self.link(nbr, dens, p, ids=ids, padded=padded, stream=stream)
+        root, chain_of, nc = self.groups(hop, dens, p, ids=ids, stream=stream)
+        out = self.merge(nbr, dens, root, chain_of, nc, p, ids=ids, padded=padded,
+                         stream=stream)
+        out.update(density=dens, nbr=nbr, hop=hop, root=root, chain_of=chain_of, n_chains=nc)
+        return out
+
+    def set_profiling(self, on: bool):
+        self._check(self.lib.hop_set_profiling(self.h, 1 if on else 0))
+
+    def stats(self) -> dict:
+        s = _Stats()
+        self._check(self.lib.hop_get_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in _Stats._fields_}

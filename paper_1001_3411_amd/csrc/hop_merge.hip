@@ -1,0 +1,569 @@
+// hop_merge.hip -- chain boundaries, merge and group labels (the paper's
+// section 2, merge steps 2-5, and the output rules of section 3.1).
+//
+// Boundaries.  Every chained particle offers its n_merge-1 nearest others
+// that sit in a different chain; the boundary density 0.5*(d_i + d_j) of the
+// chain pair is kept by a 64-bit atomic max in an open-addressing hash
+// table keyed by (lo << 32 | hi).  Boundary densities are >= 0, so their
+// IEEE bit patterns order like the values and the max runs on the bits.
+//
+// Merge.  Proto-halos (peak >= delta_peak) all start in the component of a
+// virtual root; Boruvka rounds then build the maximum spanning forest of
+// the chain graph under the strict order (s desc, lo asc, hi asc): every
+// component picks its best outgoing boundary (an atomic max on s, then an
+// atomic min on the pair key among equal s) and hooks to the other side.
+// That forest is unique, and in it every sub-peak chain reaches a proto-halo
+// through its densest chain of boundaries, or reaches none.  Halos are the
+// connected pieces of forest edges plus the proto-halo pairs with a
+// boundary >= delta_saddle, found with a lock-free union-find whose roots
+// are the smallest chain of each piece.
+//
+// Labels.  Halo sizes and peaks by atomics, then three stable radix sorts
+// order the halos by (count desc, peak density desc, peak tie key asc).
+#include "hop_internal.h"
+
+#include <algorithm>
+
+namespace {
+
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ __forceinline__ uint64_t pair_hash(uint64_t k)
+{
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+__global__ void k_chain_table(int64_t n, const int32_t *__restrict__ root,
+                              const int32_t *__restrict__ chain_of, const double *__restrict__ dens,
+                              int32_t C, int32_t *__restrict__ croot, double *__restrict__ cpeak,
+                              uint32_t *__restrict__ dflags)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = chain_of[i];
+    if (c < -1 || c >= C) {
+        atomicOr(dflags, DERR_INDEX);
+        return;
+    }
+    int32_t r = root[i];
+    if (r < 0 || r >= n) {
+        atomicOr(dflags, DERR_INDEX);
+        return;
+    }
+    if (c >= 0 && r == (int32_t)i) {
+        croot[c] = (int32_t)i;
+        cpeak[c] = dens[i];
+    }
+}
+
+__global__ void k_saddle_insert(int64_t n, const int32_t *__restrict__ nbr, int k_store,
+                                int n_merge, const double *__restrict__ dens,
+                                const int32_t *__restrict__ chain_of,
+                                const uint8_t *__restrict__ padded, int padded_rules, int32_t C,
+                                uint64_t *__restrict__ hkeys, unsigned long long *__restrict__ hvals,
+                                uint64_t mask, int log2cap, uint32_t *__restrict__ dflags)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t ci = chain_of[i];
+    if (ci < 0 || ci >= C) return;
+    const bool pi = padded_rules && padded && padded[i];
+    const double di = dens[i];
+    for (int t = 1; t < n_merge; t++) {
+        const int32_t j = nbr[i * k_store + t];
+        if (j < 0 || j >= n) {
+            atomicOr(dflags, DERR_INDEX);
+            continue;
+        }
+        const int32_t cj = chain_of[j];
+        if (cj < 0 || cj >= C || cj == ci) continue;
+        if (pi && padded[j]) continue;
+        const double sv = (di + dens[j]) * 0.5;
+        const unsigned long long sb = (unsigned long long)__double_as_longlong(sv);
+        const uint64_t key = ((uint64_t)(uint32_t)min(ci, cj) << 32) | (uint32_t)max(ci, cj);
+        uint64_t slot = pair_hash(key) >> (64 - log2cap);
+        bool done = false;
+        for (uint64_t probe = 0; probe <= mask; probe++) {
+            uint64_t k = hkeys[slot];
+            if (k == kEmpty) {
+                k = atomicCAS((unsigned long long *)&hkeys[slot], (unsigned long long)kEmpty,
+                              (unsigned long long)key);
+                if (k == kEmpty) k = key;
+            }
+            if (k == key) {
+                atomicMax(&hvals[slot], sb);
+                done = true;
+                break;
+            }
+            slot = (slot + 1) & mask;
+        }
+        if (!done) atomicOr(dflags, DERR_CAPACITY);
+    }
+}
+
+__global__ void k_edge_compact(int64_t cap, const uint64_t *__restrict__ hkeys,
+                               const unsigned long long *__restrict__ hvals,
+                               int32_t *__restrict__ elo, int32_t *__restrict__ ehi,
+                               uint64_t *__restrict__ es, uint32_t *__restrict__ count)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cap) return;
+    uint64_t k = hkeys[t];
+    if (k == kEmpty) return;
+    uint32_t at = atomicAdd(count, 1u);
+    elo[at] = (int32_t)(k >> 32);
+    ehi[at] = (int32_t)(k & 0xffffffffu);
+    es[at] = hvals[t];
+}
+
+__global__ void k_bor_init(int32_t C, const double *__restrict__ cpeak, double delta_peak,
+                           int32_t *__restrict__ par)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > C) return;
+    par[c] = (c < C && cpeak[c] >= delta_peak) ? C : (int32_t)c;
+}
+
+__global__ void k_bor_reset(int32_t C, unsigned long long *__restrict__ bs,
+                            unsigned long long *__restrict__ bk)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > C) return;
+    bs[c] = 0ull;
+    bk[c] = ~0ull;
+}
+
+__global__ void k_bor_best_s(int64_t E, const int32_t *__restrict__ elo,
+                             const int32_t *__restrict__ ehi, const uint64_t *__restrict__ es,
+                             const int32_t *__restrict__ par, unsigned long long *__restrict__ bs)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int32_t A = par[elo[e]], B = par[ehi[e]];
+    if (A == B) return;
+    atomicMax(&bs[A], (unsigned long long)es[e]);
+    atomicMax(&bs[B], (unsigned long long)es[e]);
+}
+
+__global__ void k_bor_best_k(int64_t E, const int32_t *__restrict__ elo,
+                             const int32_t *__restrict__ ehi, const uint64_t *__restrict__ es,
+                             const int32_t *__restrict__ par,
+                             const unsigned long long *__restrict__ bs,
+                             unsigned long long *__restrict__ bk)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int32_t A = par[elo[e]], B = par[ehi[e]];
+    if (A == B) return;
+    unsigned long long key = ((unsigned long long)(uint32_t)elo[e] << 32) | (uint32_t)ehi[e];
+    if (es[e] == bs[A]) atomicMin(&bk[A], key);
+    if (es[e] == bs[B]) atomicMin(&bk[B], key);
+}
+
+// Every root component with a best boundary hooks to the other side, except
+// the smaller-numbered side of a mutual pick.  Hooks go to tgt (applied by
+// k_bor_apply) so that par stays unchanged while this kernel reads it.
+__global__ void k_bor_hook(int32_t C, const int32_t *__restrict__ par,
+                           const unsigned long long *__restrict__ bk, int32_t *__restrict__ tgt,
+                           int32_t *__restrict__ msf_lo, int32_t *__restrict__ msf_hi,
+                           uint32_t *__restrict__ counters)
+{
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x > C) return;
+    tgt[x] = par[x];
+    if (par[x] != (int32_t)x) return;
+    unsigned long long k = bk[x];
+    if (k == ~0ull) return;
+    int32_t lo = (int32_t)(k >> 32), hi = (int32_t)(k & 0xffffffffu);
+    int32_t A = par[lo], B = par[hi];
+    int32_t other = (A == (int32_t)x) ? B : A;
+    if (bk[other] == k && (int32_t)x < other) return;  // mutual: the other side hooks
+    tgt[x] = other;
+    uint32_t at = atomicAdd(&counters[0], 1u);
+    msf_lo[at] = lo;
+    msf_hi[at] = hi;
+}
+
+__global__ void k_bor_apply(int32_t C, const int32_t *__restrict__ tgt, int32_t *__restrict__ par)
+{
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x > C) return;
+    par[x] = tgt[x];
+}
+
+// Full path compression of a static forest (no hooks run concurrently).
+// A path in a forest of m nodes has fewer than m steps, which bounds the loop.
+__global__ void k_compress(int64_t m, int32_t *__restrict__ par)
+{
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= m) return;
+    int32_t r = par[x];
+    for (int64_t guard = 0; guard < m; guard++) {
+        int32_t rr = par[r];
+        if (rr == r) break;
+        r = rr;
+    }
+    par[x] = r;
+}
+
+__global__ void k_iota(int64_t m, int32_t *__restrict__ p)
+{
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < m) p[x] = (int32_t)x;
+}
+
+__device__ __forceinline__ int32_t uf_find(const int32_t *p, int32_t x)
+{
+    for (;;) {
+        int32_t y = __atomic_load_n(&p[x], __ATOMIC_RELAXED);
+        if (y == x) return x;
+        x = y;
+    }
+}
+
+__device__ __forceinline__ void uf_union(int32_t *p, int32_t a, int32_t b)
+{
+    for (;;) {
+        a = uf_find(p, a);
+        b = uf_find(p, b);
+        if (a == b) return;
+        if (a < b) {
+            int32_t t = a;
+            a = b;
+            b = t;
+        }
+        // link the larger root under the smaller one
+        if (atomicCAS(&p[a], a, b) == a) return;
+    }
+}
+
+__global__ void k_union_msf(int64_t m, const int32_t *__restrict__ lo,
+                            const int32_t *__restrict__ hi, int32_t *__restrict__ hp)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    uf_union(hp, lo[e], hi[e]);
+}
+
+__global__ void k_union_saddle(int64_t E, const int32_t *__restrict__ elo,
+                               const int32_t *__restrict__ ehi, const uint64_t *__restrict__ es,
+                               const double *__restrict__ cpeak, double delta_peak,
+                               double delta_saddle, int32_t *__restrict__ hp)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int32_t a = elo[e], b = ehi[e];
+    double s = __longlong_as_double((long long)es[e]);
+    if (cpeak[a] >= delta_peak && cpeak[b] >= delta_peak && s >= delta_saddle) uf_union(hp, a, b);
+}
+
+__global__ void k_rooted(int32_t C, const int32_t *__restrict__ hp, const double *__restrict__ cpeak,
+                         double delta_peak, uint32_t *__restrict__ rooted)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    if (cpeak[c] >= delta_peak) rooted[hp[c]] = 1u;
+}
+
+__global__ void k_chain_count(int64_t n, const int32_t *__restrict__ chain_of,
+                              const uint8_t *__restrict__ padded, int padded_rules, int32_t C,
+                              uint32_t *__restrict__ ccount)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = chain_of[i];
+    if (c < 0 || c >= C) return;
+    if (padded_rules && padded && padded[i]) return;
+    atomicAdd(&ccount[c], 1u);
+}
+
+__global__ void k_halo_accum(int32_t C, const int32_t *__restrict__ hp,
+                             const uint32_t *__restrict__ rooted, const uint32_t *__restrict__ ccount,
+                             const double *__restrict__ cpeak, uint32_t *__restrict__ hcount,
+                             unsigned long long *__restrict__ hpeak)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    int32_t h = hp[c];
+    if (!rooted[h]) return;
+    if (ccount[c]) atomicAdd(&hcount[h], ccount[c]);
+    atomicMax(&hpeak[h], (unsigned long long)__double_as_longlong(cpeak[c]));
+}
+
+__global__ void k_halo_peak_tk(int32_t C, const int32_t *__restrict__ hp,
+                               const uint32_t *__restrict__ rooted, const double *__restrict__ cpeak,
+                               const unsigned long long *__restrict__ hpeak,
+                               const int32_t *__restrict__ croot, const int32_t *__restrict__ tk,
+                               uint32_t *__restrict__ hptk)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    int32_t h = hp[c];
+    if (!rooted[h]) return;
+    if ((unsigned long long)__double_as_longlong(cpeak[c]) != hpeak[h]) return;
+    int32_t r = croot[c];
+    atomicMin(&hptk[h], (uint32_t)(tk ? tk[r] : r));
+}
+
+// halos with at least one labelled particle -> compact list, sort key = peak tie key
+__global__ void k_halo_list(int32_t C, const int32_t *__restrict__ hp,
+                            const uint32_t *__restrict__ rooted, const uint32_t *__restrict__ hcount,
+                            const uint32_t *__restrict__ hptk, uint64_t *__restrict__ keys,
+                            uint32_t *__restrict__ vals, uint32_t *__restrict__ counter)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    if (hp[c] != (int32_t)c || !rooted[c] || hcount[c] == 0) return;
+    uint32_t at = atomicAdd(counter, 1u);
+    keys[at] = hptk[c];
+    vals[at] = (uint32_t)c;
+}
+
+__global__ void k_key_peak(int64_t G, const uint32_t *__restrict__ vals,
+                           const unsigned long long *__restrict__ hpeak, uint64_t *__restrict__ keys)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= G) return;
+    keys[t] = ~(uint64_t)hpeak[vals[t]];  // descending density
+}
+
+__global__ void k_key_count(int64_t G, const uint32_t *__restrict__ vals,
+                            const uint32_t *__restrict__ hcount, uint64_t *__restrict__ keys)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= G) return;
+    keys[t] = (uint64_t)(~hcount[vals[t]]);  // descending count (32 bits)
+}
+
+__global__ void k_number(int64_t G, const uint32_t *__restrict__ vals,
+                         const uint32_t *__restrict__ hcount,
+                         const unsigned long long *__restrict__ hpeak,
+                         const uint32_t *__restrict__ hptk, const int32_t *__restrict__ tk2j,
+                         int32_t *__restrict__ num, hop_group_info *__restrict__ out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= G) return;
+    uint32_t h = vals[t];
+    num[h] = (int32_t)t;
+    if (out) {
+        hop_group_info g;
+        g.count = hcount[h];
+        uint32_t ptk = hptk[h];
+        g.peak = tk2j ? tk2j[ptk] : (int32_t)ptk;
+        g.reserved = 0;
+        g.peak_density = __longlong_as_double((long long)hpeak[h]);
+        out[t] = g;
+    }
+}
+
+__global__ void k_group(int64_t n, const int32_t *__restrict__ chain_of, int32_t C,
+                        const int32_t *__restrict__ hp, const uint32_t *__restrict__ rooted,
+                        const int32_t *__restrict__ num, const uint8_t *__restrict__ padded,
+                        int padded_rules, int32_t *__restrict__ group)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = chain_of[i];
+    int32_t g = -1;
+    if (c >= 0 && c < C && !(padded_rules && padded && padded[i])) {
+        int32_t h = hp[c];
+        if (rooted[h]) g = num[h];
+    }
+    group[i] = g;
+}
+
+__global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+// carve aligned sub-arrays out of one buffer
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(int64_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = (T *)(base + off);
+        off += (size_t)count * sizeof(T);
+        return p;
+    }
+};
+
+inline int64_t pow2ceil(int64_t v)
+{
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
+                   const int32_t *root, const int32_t *chain_of, int32_t n_chains,
+                   const int32_t *tk, const uint8_t *padded, const hop_params *p, int32_t *group,
+                   int32_t *n_groups, hop_group_info *groups, hipStream_t s)
+{
+    uint32_t *dflags = (uint32_t *)ctx->flags.ptr;
+    uint32_t *dcnt = dflags + 4;  // [0] edges, [1] msf edges, [2] halos
+    const int32_t C = n_chains;
+    const int pr = (p->flags & HOP_PADDED_RULES) ? 1 : 0;
+    const int32_t *tk2j = tk ? (const int32_t *)ctx->tk2j.ptr : nullptr;
+    if (C <= 0) {
+        k_fill_i32<<<hop_grid(n, 256), 256, 0, s>>>(group, n, -1);
+        HOPCHK(ctx, hipGetLastError());
+        HOPTRY(hop_check_device(ctx, s, "hop_merge"));
+        *n_groups = 0;
+        return HOP_OK;
+    }
+
+    // workspace for the chain-sized arrays
+    const int64_t C1 = (int64_t)C + 1;
+    size_t need = 0;
+    need += (size_t)C1 * (4 + 8 + 4 + 4 + 8 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4 + 4 + 4) + 20 * 256;
+    HOPTRY(hop_reserve(ctx, ctx->work_b, need));
+    Carver cv{(char *)ctx->work_b.ptr};
+    int32_t *croot = cv.take<int32_t>(C1);
+    double *cpeak = cv.take<double>(C1);
+    int32_t *par = cv.take<int32_t>(C1);
+    int32_t *tgt = cv.take<int32_t>(C1);
+    unsigned long long *bs = cv.take<unsigned long long>(C1);
+    unsigned long long *bk = cv.take<unsigned long long>(C1);
+    int32_t *msf_lo = cv.take<int32_t>(C1);
+    int32_t *msf_hi = cv.take<int32_t>(C1);
+    int32_t *hp = cv.take<int32_t>(C1);
+    uint32_t *rooted = cv.take<uint32_t>(C1);
+    unsigned long long *hpeak = cv.take<unsigned long long>(C1);
+    uint32_t *hptk = cv.take<uint32_t>(C1);
+    uint32_t *ccount = cv.take<uint32_t>(C1);
+    uint32_t *hcount = cv.take<uint32_t>(C1);
+    int32_t *num = cv.take<int32_t>(C1);
+
+    k_chain_table<<<hop_grid(n, 256), 256, 0, s>>>(n, root, chain_of, density, C, croot, cpeak, dflags);
+    HOPCHK(ctx, hipGetLastError());
+
+    // --- boundary table -----------------------------------------------------
+    const int64_t pairs_max = (int64_t)(p->n_merge - 1) * n;
+    int64_t cap = pow2ceil(std::max<int64_t>(4096, std::min<int64_t>(16 * (int64_t)C, 2 * pairs_max + 1)));
+    const int64_t cap_max = pow2ceil(2 * pairs_max + 1);
+    int64_t E = 0;
+    for (;;) {
+        int log2cap = 0;
+        while (((int64_t)1 << log2cap) < cap) log2cap++;
+        HOPTRY(hop_reserve(ctx, ctx->hash_keys, (size_t)cap * 8));
+        HOPTRY(hop_reserve(ctx, ctx->hash_vals, (size_t)cap * 8));
+        uint64_t *hk = (uint64_t *)ctx->hash_keys.ptr;
+        unsigned long long *hv = (unsigned long long *)ctx->hash_vals.ptr;
+        HOPCHK(ctx, hipMemsetAsync(hk, 0xff, (size_t)cap * 8, s));
+        HOPCHK(ctx, hipMemsetAsync(hv, 0, (size_t)cap * 8, s));
+        HOPCHK(ctx, hipMemsetAsync(dcnt, 0, 16, s));
+        k_saddle_insert<<<hop_grid(n, 256), 256, 0, s>>>(n, nbr, p->k_store, p->n_merge, density,
+                                                        chain_of, padded, pr, C, hk, hv,
+                                                        (uint64_t)(cap - 1), log2cap, dflags);
+        HOPCHK(ctx, hipGetLastError());
+        HOPCHK(ctx, hipMemcpyAsync(ctx->hflags + 2, dflags, 4, hipMemcpyDeviceToHost, s));
+        HOPCHK(ctx, hipStreamSynchronize(s));
+        uint32_t fl = (uint32_t)ctx->hflags[2];
+        if ((fl & DERR_CAPACITY) && cap < cap_max) {
+            // keep any other error bits, drop the capacity bit, retry larger
+            ctx->hflags[3] = (int64_t)(fl & ~DERR_CAPACITY);
+            HOPCHK(ctx, hipMemcpyAsync(dflags, &ctx->hflags[3], 4, hipMemcpyHostToDevice, s));
+            cap *= 2;
+            continue;
+        }
+        HOPTRY(hop_reserve(ctx, ctx->edges_lo, (size_t)cap * 4));
+        HOPTRY(hop_reserve(ctx, ctx->edges_hi, (size_t)cap * 4));
+        HOPTRY(hop_reserve(ctx, ctx->edges_s, (size_t)cap * 8));
+        k_edge_compact<<<hop_grid(cap, 256), 256, 0, s>>>(
+            cap, hk, hv, (int32_t *)ctx->edges_lo.ptr, (int32_t *)ctx->edges_hi.ptr,
+            (uint64_t *)ctx->edges_s.ptr, dcnt);
+        HOPCHK(ctx, hipGetLastError());
+        HOPCHK(ctx, hipMemcpyAsync(ctx->hflags + 2, dcnt, 4, hipMemcpyDeviceToHost, s));
+        HOPCHK(ctx, hipStreamSynchronize(s));
+        E = (int64_t)(uint32_t)ctx->hflags[2];
+        break;
+    }
+    const int32_t *elo = (const int32_t *)ctx->edges_lo.ptr;
+    const int32_t *ehi = (const int32_t *)ctx->edges_hi.ptr;
+    const uint64_t *es = (const uint64_t *)ctx->edges_s.ptr;
+
+    // --- maximum spanning forest with a virtual root (Boruvka) --------------
+    k_bor_init<<<hop_grid(C1, 256), 256, 0, s>>>(C, cpeak, p->delta_peak, par);
+    HOPCHK(ctx, hipGetLastError());
+    HOPCHK(ctx, hipMemsetAsync(dcnt + 1, 0, 4, s));  // msf edge counter
+    for (int round = 0; round < 64; round++) {
+        HOPCHK(ctx, hipMemsetAsync(dcnt + 2, 0, 4, s));
+        uint32_t before = 0;
+        HOPCHK(ctx, hipMemcpyAsync(&ctx->hflags[4], dcnt + 1, 4, hipMemcpyDeviceToHost, s));
+        k_bor_reset<<<hop_grid(C1, 256), 256, 0, s>>>(C, bs, bk);
+        k_bor_best_s<<<hop_grid(E, 256), 256, 0, s>>>(E, elo, ehi, es, par, bs);
+        k_bor_best_k<<<hop_grid(E, 256), 256, 0, s>>>(E, elo, ehi, es, par, bs, bk);
+        k_bor_hook<<<hop_grid(C1, 256), 256, 0, s>>>(C, par, bk, tgt, msf_lo, msf_hi, dcnt + 1);
+        k_bor_apply<<<hop_grid(C1, 256), 256, 0, s>>>(C, tgt, par);
+        k_compress<<<hop_grid(C1, 256), 256, 0, s>>>(C1, par);
+        HOPCHK(ctx, hipGetLastError());
+        HOPCHK(ctx, hipMemcpyAsync(&ctx->hflags[5], dcnt + 1, 4, hipMemcpyDeviceToHost, s));
+        HOPCHK(ctx, hipStreamSynchronize(s));
+        before = (uint32_t)ctx->hflags[4];
+        uint32_t after = (uint32_t)ctx->hflags[5];
+        if (after == before) break;
+        if (round == 63) return hop_fail(ctx, HOP_ERR_ARG, "merge did not converge");
+    }
+    const int64_t M = (int64_t)(uint32_t)ctx->hflags[5];
+
+    // --- halos: forest edges + proto-halo saddles ---------------------------
+    k_iota<<<hop_grid(C, 256), 256, 0, s>>>(C, hp);
+    if (M > 0) k_union_msf<<<hop_grid(M, 256), 256, 0, s>>>(M, msf_lo, msf_hi, hp);
+    if (E > 0)
+        k_union_saddle<<<hop_grid(E, 256), 256, 0, s>>>(E, elo, ehi, es, cpeak, p->delta_peak,
+                                                        p->delta_saddle, hp);
+    k_compress<<<hop_grid(C, 256), 256, 0, s>>>(C, hp);
+    HOPCHK(ctx, hipMemsetAsync(rooted, 0, (size_t)C * 4, s));
+    k_rooted<<<hop_grid(C, 256), 256, 0, s>>>(C, hp, cpeak, p->delta_peak, rooted);
+    HOPCHK(ctx, hipGetLastError());
+
+    // --- labels --------------------------------------------------------------
+    HOPCHK(ctx, hipMemsetAsync(ccount, 0, (size_t)C * 4, s));
+    HOPCHK(ctx, hipMemsetAsync(hcount, 0, (size_t)C * 4, s));
+    HOPCHK(ctx, hipMemsetAsync(hpeak, 0, (size_t)C * 8, s));
+    HOPCHK(ctx, hipMemsetAsync(hptk, 0xff, (size_t)C * 4, s));
+    k_chain_count<<<hop_grid(n, 256), 256, 0, s>>>(n, chain_of, padded, pr, C, ccount);
+    k_halo_accum<<<hop_grid(C, 256), 256, 0, s>>>(C, hp, rooted, ccount, cpeak, hcount, hpeak);
+    k_halo_peak_tk<<<hop_grid(C, 256), 256, 0, s>>>(C, hp, rooted, cpeak, hpeak, croot, tk, hptk);
+    HOPCHK(ctx, hipGetLastError());
+    HOPTRY(hop_reserve(ctx, ctx->keys_a, (size_t)C * 8));
+    HOPTRY(hop_reserve(ctx, ctx->keys_b, (size_t)C * 8));
+    HOPTRY(hop_reserve(ctx, ctx->vals_a, (size_t)C * 4));
+    HOPTRY(hop_reserve(ctx, ctx->vals_b, (size_t)C * 4));
+    uint64_t *keys = (uint64_t *)ctx->keys_a.ptr;
+    uint32_t *vals = (uint32_t *)ctx->vals_a.ptr;
+    HOPCHK(ctx, hipMemsetAsync(dcnt + 2, 0, 4, s));
+    k_halo_list<<<hop_grid(C, 256), 256, 0, s>>>(C, hp, rooted, hcount, hptk, keys, vals, dcnt + 2);
+    HOPCHK(ctx, hipGetLastError());
+    HOPCHK(ctx, hipMemcpyAsync(&ctx->hflags[6], dcnt + 2, 4, hipMemcpyDeviceToHost, s));
+    HOPCHK(ctx, hipStreamSynchronize(s));
+    const int64_t G = (int64_t)(uint32_t)ctx->hflags[6];
+    uint64_t *tkeys = (uint64_t *)ctx->keys_b.ptr;
+    uint32_t *tvals = (uint32_t *)ctx->vals_b.ptr;
+    if (G > 1) {
+        HOPTRY(hop_radix_sort(ctx, keys, vals, tkeys, tvals, G, 32, s));
+        k_key_peak<<<hop_grid(G, 256), 256, 0, s>>>(G, vals, hpeak, keys);
+        HOPTRY(hop_radix_sort(ctx, keys, vals, tkeys, tvals, G, 64, s));
+        k_key_count<<<hop_grid(G, 256), 256, 0, s>>>(G, vals, hcount, keys);
+        HOPTRY(hop_radix_sort(ctx, keys, vals, tkeys, tvals, G, 32, s));
+    }
+    if (G > 0)
+        k_number<<<hop_grid(G, 256), 256, 0, s>>>(G, vals, hcount, hpeak, hptk, tk2j, num, groups);
+    k_group<<<hop_grid(n, 256), 256, 0, s>>>(n, chain_of, C, hp, rooted, num, padded, pr, group);
+    HOPCHK(ctx, hipGetLastError());
+    HOPTRY(hop_check_device(ctx, s, "hop_merge"));
+    *n_groups = (int32_t)G;
+    return HOP_OK;
+}

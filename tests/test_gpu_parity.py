@@ -1,0 +1,172 @@
+"""GPU parity: every stage of the HIP path against the CPU oracle, element by
+element, on the same seeded inputs.  Integer outputs (neighbour lists, links,
+roots, chains, groups) must match exactly; FP64 densities must match bit for
+bit because both sides run the same operation sequence (exact integer d^2,
+correctly rounded division and square root, no contraction, pairwise sum).
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1001_3411_amd import HopContext
+    c = HopContext(0)
+    yield c
+    c.close()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def gpu_run(ctx, p, params, ids=None):
+    out = ctx.run(p.pos, params, ids=ids, padded=p.padded)
+    return {k: (_np(v) if hasattr(v, "detach") else v) for k, v in out.items()}
+
+
+def _params(p, **kw):
+    from paper_1001_3411_amd import HopParams
+    return HopParams(periodic=p.periodic, mean_density=p.mean_density, **kw)
+
+
+def assert_parity(g, r, label=""):
+    print(f"[parity] {label}", flush=True)
+    assert np.array_equal(g["nbr"], r.nbr), f"{label}: nbr"
+    bad = np.flatnonzero(g["density"] != r.density)
+    assert bad.size == 0, f"{label}: density differs at {bad[:5]} " \
+                          f"{g['density'][bad[:3]]} vs {r.density[bad[:3]]}"
+    assert np.array_equal(g["hop"], r.hop), f"{label}: hop"
+    assert np.array_equal(g["root"], r.root), f"{label}: root"
+    assert np.array_equal(g["chain_of"], r.chain_of), f"{label}: chain_of"
+    assert g["n_chains"] == r.n_chains, label
+    assert g["n_groups"] == r.n_groups, f"{label}: n_groups {g['n_groups']} vs {r.n_groups}"
+    assert np.array_equal(g["group"], r.group), f"{label}: group"
+    assert np.array_equal(g["g_count"], r.g_count), f"{label}: g_count"
+    assert np.array_equal(g["g_peak"], r.g_peak), f"{label}: g_peak"
+    assert np.array_equal(g["g_peak_dens"], r.g_peak_dens), f"{label}: g_peak_dens"
+
+
+CASES = [("uniform", 64, 1), ("uniform", 100, 2), ("uniform", 1000, 3), ("clustered", 1000, 4),
+         ("clustered", 4096, 5), ("lattice", 4096, 6), ("plattice", 4096, 7),
+         ("uniform", 4097, 8)]
+
+
+@pytest.mark.parametrize("kind,n,seed", CASES)
+def test_tiny_cases_full_pipeline(ctx, orc, kind, n, seed):
+    p = synth.tiny_case(kind, n, seed)
+    prm = orc.HopParams()
+    if kind in ("uniform", "lattice", "plattice"):
+        # uniform-ish sets never reach 80x the mean: lower the thresholds so
+        # that chains, boundaries and merges all occur
+        prm = orc.HopParams(delta_outer=0.9, delta_saddle=1.2, delta_peak=1.4)
+    r = orc.run(p.pos, mean_density=p.mean_density, params=prm)
+    g = gpu_run(ctx, p, _params(p, delta_outer=prm.delta_outer, delta_saddle=prm.delta_saddle,
+                                delta_peak=prm.delta_peak))
+    assert_parity(g, r, f"{kind}-{n}-{seed}")
+
+
+def test_config1_full_pipeline(ctx, orc):
+    p = synth.config(1)
+    r = orc.run(p.pos, mean_density=p.mean_density)
+    g = gpu_run(ctx, p, _params(p))
+    assert r.n_groups > 5
+    assert_parity(g, r, "config1")
+
+
+def test_nonperiodic_padded_subvolume(ctx, orc):
+    p = synth.padded_subvolume(20000, 31)
+    r = orc.run(p.pos, periodic=False, mean_density=p.mean_density, padded=p.padded,
+                padded_rules=True)
+    g = gpu_run(ctx, p, _params(p, padded_rules=True))
+    assert_parity(g, r, "subvolume-padded")
+
+
+def test_nonperiodic_without_padded_rules(ctx, orc):
+    p = synth.padded_subvolume(12000, 32)
+    r = orc.run(p.pos, periodic=False, mean_density=p.mean_density)
+    p.padded = None
+    g = gpu_run(ctx, p, _params(p))
+    assert_parity(g, r, "subvolume-plain")
+
+
+def test_ids_permutation(ctx, orc):
+    p = synth.lattice_box(16)
+    perm = np.random.default_rng(5).permutation(p.n)
+    ids = (perm.astype(np.int64) * 7 - 3000)
+    prm = orc.HopParams(delta_outer=0.5, delta_saddle=0.6, delta_peak=0.7)
+    r = orc.run(p.pos[perm], ids=ids, params=prm)
+    q = synth.Particles(pos=np.ascontiguousarray(p.pos[perm]), periodic=True,
+                        mean_density=p.mean_density)
+    g = gpu_run(ctx, q, _params(q, delta_outer=0.5, delta_saddle=0.6, delta_peak=0.7), ids=ids)
+    assert_parity(g, r, "lattice-ids")
+
+
+def test_small_kstore_and_ndens(ctx, orc):
+    p = synth.tiny_case("clustered", 4096, 9)
+    prm = orc.HopParams(n_dens=32, n_hop=8, n_merge=3, k_store=16)
+    r = orc.run(p.pos, mean_density=p.mean_density, params=prm)
+    g = gpu_run(ctx, p, _params(p, n_dens=32, n_hop=8, n_merge=3, k_store=16))
+    assert_parity(g, r, "ndens32")
+
+
+def test_stages_on_oracle_inputs(ctx, orc):
+    """Each GPU stage fed with the oracle's own upstream outputs."""
+    import torch
+    p = synth.config(1)
+    r = orc.run(p.pos, mean_density=p.mean_density)
+    prm = _params(p)
+    dev = "cuda:0"
+    nbr = torch.from_numpy(r.nbr).to(dev)
+    dens = torch.from_numpy(r.density).to(dev)
+    hop = ctx.link(nbr, dens, prm)
+    assert np.array_equal(_np(hop), r.hop)
+    root, chain_of, nc = ctx.groups(torch.from_numpy(r.hop).to(dev), dens, prm)
+    assert np.array_equal(_np(root), r.root) and np.array_equal(_np(chain_of), r.chain_of)
+    out = ctx.merge(nbr, dens, torch.from_numpy(r.root).to(dev),
+                    torch.from_numpy(r.chain_of).to(dev), r.n_chains, prm)
+    assert out["n_groups"] == r.n_groups
+    assert np.array_equal(_np(out["group"]), r.group)
+
+
+def test_determinism_two_runs(ctx):
+    p = synth.config(1)
+    a = gpu_run(ctx, p, _params(p))
+    b = gpu_run(ctx, p, _params(p))
+    for k in ("nbr", "density", "hop", "group"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_config2_full_pipeline(ctx, orc):
+    p = synth.config(2)
+    r = orc.run(p.pos, mean_density=p.mean_density)
+    g = gpu_run(ctx, p, _params(p))
+    assert_parity(g, r, "config2")
+
+
+def test_range_error_reported(ctx):
+    from paper_1001_3411_amd import HopError
+    p = synth.uniform_box(500, 3)
+    pos = p.pos.copy()
+    pos[7, 1] = 1 << 21
+    with pytest.raises(HopError) as e:
+        gpu_run(ctx, synth.Particles(pos=pos, periodic=True, mean_density=p.mean_density),
+                _params(p))
+    assert e.value.code == -2
+
+
+def test_degenerate_reported(ctx):
+    from paper_1001_3411_amd import HopError
+    pos = np.zeros((200, 3), np.uint32)
+    pos[100:] = 777
+    with pytest.raises(HopError) as e:
+        gpu_run(ctx, synth.Particles(pos=pos, periodic=True, mean_density=200 / 2.0 ** 63),
+                _params(synth.Particles(pos=pos, periodic=True, mean_density=200 / 2.0 ** 63)))
+    assert e.value.code == -3
