@@ -214,8 +214,9 @@ typedef struct hop_stats {
     int64_t leaves_scanned; /* leaves whose points were tested                   */
 } hop_stats;
 
-/* Turns device-side counters and per-stage timing on or off (default off);
-   timing synchronises the stream inside hop_density. */
+/* Profiling bits (default 0): 1 = time the sort/tree and kNN stages of
+   hop_density with HIP events (synchronises the stream inside the call);
+   2 = also count tree nodes tested and leaves scanned (device atomics). */
 int hop_set_profiling(hop_ctx *ctx, int on);
 int hop_get_stats(const hop_ctx *ctx, hop_stats *out);
 

@@ -251,7 +251,7 @@ class HopContext:
         return out
 
     def set_profiling(self, on: bool):
-        self._check(self.lib.hop_set_profiling(self.h, 1 if on else 0))
+        self._check(self.lib.hop_set_profiling(self.h, int(on)))
 
     def stats(self) -> dict:
         s = _Stats()

@@ -163,7 +163,7 @@ const char *hop_last_error(const hop_ctx *ctx)
 int hop_set_profiling(hop_ctx *ctx, int on)
 {
     if (!ctx) return HOP_ERR_ARG;
-    ctx->profiling = on ? 1 : 0;
+    ctx->profiling = on & 3;
     return HOP_OK;
 }
 

@@ -574,8 +574,9 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     a.tk2j = tk2j;
     a.dflags = dflags;
     a.counters = nullptr;
-    if (ctx->profiling) {
-        a.counters = (unsigned long long *)((char *)ctx->flags.ptr + 256);
+    unsigned long long *counters = (unsigned long long *)((char *)ctx->flags.ptr + 256);
+    if (ctx->profiling & 2) {
+        a.counters = counters;
         HOPCHK(ctx, hipMemsetAsync(a.counters, 0, 16, s));
     }
     const int64_t grid = a.xcd_chunk * 8;
@@ -596,7 +597,7 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
         HOPCHK(ctx, hipEventElapsedTime(&t0, ev[0], ev[1]));
         HOPCHK(ctx, hipEventElapsedTime(&t1, ev[1], ev[2]));
         unsigned long long c[2] = {0, 0};
-        HOPCHK(ctx, hipMemcpy(c, a.counters, 16, hipMemcpyDeviceToHost));
+        if (a.counters) HOPCHK(ctx, hipMemcpy(c, a.counters, 16, hipMemcpyDeviceToHost));
         ctx->stats.ms_sort = t0;
         ctx->stats.ms_knn = t1;
         ctx->stats.n = n;
