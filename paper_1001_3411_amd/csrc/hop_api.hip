@@ -1,6 +1,7 @@
 // hop_api.hip -- the C ABI: context, validation, error reporting and the four
 // stage entry points declared in include/hop.h.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -126,6 +127,7 @@ int hop_ctx_create(int device, hop_ctx **out)
     hop_ctx *ctx = new (std::nothrow) hop_ctx();
     if (!ctx) return HOP_ERR_NOMEM;
     ctx->device = device;
+    if (const char *fc = std::getenv("HOP_FRONT_CAP")) ctx->front_cap = std::atoi(fc);
     int rc = set_device(ctx);
     if (rc == HOP_OK) rc = hop_reserve(ctx, ctx->flags, 4096);
     if (rc == HOP_OK && hipMemset(ctx->flags.ptr, 0, 4096) != hipSuccess) rc = HOP_ERR_HIP;

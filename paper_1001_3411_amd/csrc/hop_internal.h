@@ -56,6 +56,10 @@ struct hop_ctx {
     int device = 0;
     std::string err;
     int profiling = 0;
+    // frontier capacity of the kNN walk; lowering it (environment variable
+    // HOP_FRONT_CAP, read at context creation) routes buckets to the exact
+    // depth-first fallback, which the tests use to cover that path
+    int front_cap = 1 << 30;
     hop_stats stats{};
 
     // device scratch

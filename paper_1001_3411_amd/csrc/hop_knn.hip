@@ -26,6 +26,8 @@
 // correctly rounded division and square root and no contraction.
 #include "hop_internal.h"
 
+#include <algorithm>
+
 namespace {
 
 __device__ __forceinline__ uint64_t spread3(uint32_t v)
@@ -116,7 +118,8 @@ __global__ void k_level_boxes(NodeBox *__restrict__ boxes, int64_t child_off, in
 // kNN + density
 // ---------------------------------------------------------------------------
 
-constexpr int kHeapMax = 63;  // n_dens - 1 <= 63
+constexpr int kHeapMax = 63;   // n_dens - 1 <= 63
+constexpr int kHeapSlots = 65; // 4-ary heap: slots up to 4*15+4 are read
 
 struct KnnArgs {
     const SortedRec *recs;
@@ -134,6 +137,7 @@ struct KnnArgs {
     double norm;         // 1 / (pi * mean_density)
     double gsize;        // 2^grid_bits
     uint32_t gmask;
+    int front_cap;       // frontier entries the walk may use (<= kFront)
     int vec_store;       // nbr rows 16-byte aligned with k_store % 4 == 0
     int32_t *nbr;
     double *dens;
@@ -142,10 +146,21 @@ struct KnnArgs {
     unsigned long long *counters;  // [0] nodes tested, [1] leaves scanned (NULL = off)
 };
 
+// (d^2 << shift) | tk.  d^2 is an exact integer below 2^52 held in a double:
+// adding 2^52 places it in the low mantissa bits, so two instructions give
+// its integer value.
 __device__ __forceinline__ uint64_t make_key(double d2, uint32_t tk, const KnnArgs &a)
 {
-    double c = d2 < a.maxd2 ? d2 : a.maxd2;
-    return ((uint64_t)c << a.shift) | (uint64_t)tk;
+    double c = fmin(d2, a.maxd2) + 4503599627370496.0;  // + 2^52, exact
+    uint64_t m = (uint64_t)__double_as_longlong(c) & 0xfffffffffffffull;
+    return (m << a.shift) | (uint64_t)tk;
+}
+
+__device__ __forceinline__ double key_d2(uint64_t key, int shift)
+{
+    // d^2 < 2^52: rebuild the double from its integer value the same way
+    uint64_t m = key >> shift;
+    return __longlong_as_double((long long)(m | 0x4330000000000000ull)) - 4503599627370496.0;
 }
 
 // M4 cubic-spline shape without the 1/(pi h^3) factor, q2 = (r/h)^2.
@@ -171,51 +186,162 @@ __device__ __forceinline__ double axis_gap(uint32_t x, uint32_t lo, uint32_t hi,
     }
 }
 
-// Heap of one lane: slot s at heap[s * 64 + lane].
+template <bool PERIODIC>
+__device__ __forceinline__ double box_d2(uint32_t ux, uint32_t uy, uint32_t uz, const NodeBox &b,
+                                         uint32_t gmask)
+{
+    double gx = axis_gap<PERIODIC>(ux, b.lo[0], b.hi[0], gmask);
+    double gy = axis_gap<PERIODIC>(uy, b.lo[1], b.hi[1], gmask);
+    double gz = axis_gap<PERIODIC>(uz, b.lo[2], b.hi[2], gmask);
+    return __builtin_fma(gx, gx, __builtin_fma(gy, gy, gz * gz));
+}
+
+// 4-ary max-heap of one lane: slot s at heap[s * 64 + lane]; slots in
+// [hs, kHeapSlots) hold 0 so that missing children never win.
 __device__ __forceinline__ void heap_sift(uint64_t *heap, int lane, int hs, int i, uint64_t x)
 {
     for (;;) {
-        int l = 2 * i + 1;
-        if (l >= hs) break;
-        uint64_t kc = heap[l * 64 + lane];
-        int c = l;
-        if (l + 1 < hs) {
-            uint64_t kr = heap[(l + 1) * 64 + lane];
-            if (kr > kc) {
-                kc = kr;
-                c = l + 1;
-            }
-        }
-        if (kc <= x) break;
-        heap[i * 64 + lane] = kc;
-        i = c;
+        const int c = 4 * i + 1;
+        if (c >= hs) break;
+        uint64_t k0 = heap[c * 64 + lane], k1 = heap[(c + 1) * 64 + lane];
+        uint64_t k2 = heap[(c + 2) * 64 + lane], k3 = heap[(c + 3) * 64 + lane];
+        int m01 = k1 > k0 ? c + 1 : c;
+        uint64_t v01 = k1 > k0 ? k1 : k0;
+        int m23 = k3 > k2 ? c + 3 : c + 2;
+        uint64_t v23 = k3 > k2 ? k3 : k2;
+        int m = v23 > v01 ? m23 : m01;
+        uint64_t v = v23 > v01 ? v23 : v01;
+        if (v <= x) break;
+        heap[i * 64 + lane] = v;
+        i = m;
     }
     heap[i * 64 + lane] = x;
 }
 
-// Exact squared distance of this lane's query to a staged particle.
-template <bool PERIODIC>
-__device__ __forceinline__ double pair_d2(double qx, double qy, double qz, const SortedRec &p,
-                                          bool fast, double gsize)
+__device__ __forceinline__ double d2_direct(double qx, double qy, double qz, const SortedRec &p)
 {
     double dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
-    if (PERIODIC && !fast) {
-        dx = fabs(dx);
-        dy = fabs(dy);
-        dz = fabs(dz);
-        dx = fmin(dx, gsize - dx);
-        dy = fmin(dy, gsize - dy);
-        dz = fmin(dz, gsize - dz);
-    }
     return __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
 }
 
-template <bool PERIODIC, bool IDS>
-__global__ __launch_bounds__(64) void k_knn_density(KnnArgs a)
+__device__ __forceinline__ double d2_wrap(double qx, double qy, double qz, const SortedRec &p,
+                                          double gsize)
 {
-    __shared__ uint64_t heap[kHeapMax * 64];
+    double dx = fabs(qx - p.x), dy = fabs(qy - p.y), dz = fabs(qz - p.z);
+    dx = fmin(dx, gsize - dx);
+    dy = fmin(dy, gsize - dy);
+    dz = fmin(dz, gsize - dz);
+    return __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+}
+
+constexpr int kFrontLevel = 4096;  // frontier entries per level of the breadth-first walk
+constexpr int kLeafList = 1024;    // leaves the walk may hand to the streaming passes
+constexpr int kFront = kLeafList;  // largest frontier_cap honoured
+
+// Squared gap between two boxes (minimum image when periodic).
+template <bool PERIODIC>
+__device__ __forceinline__ double boxbox_d2(const NodeBox &p, const NodeBox &q, uint32_t gmask)
+{
+    double g2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const uint32_t a1 = p.lo[k], b1 = p.hi[k], a2 = q.lo[k], b2 = q.hi[k];
+        double g = 0.0;
+        if (!(a1 <= b2 && a2 <= b1)) {
+            if (PERIODIC) g = (double)min((a2 - b1) & gmask, (a1 - b2) & gmask);
+            else g = (double)max((int)a2 - (int)b1, (int)a1 - (int)b2);
+        }
+        g2 = __builtin_fma(g, g, g2);
+    }
+    return g2;
+}
+
+// Codes for the radix selection: the top bits of an exact integer d^2 held
+// in a double (sign, 11 exponent bits, leading mantissa bits) grow with d^2.
+// code4 steps by a quarter octave, code16 by a sixteenth of an octave.
+__device__ __forceinline__ int d2_code4(double d2)
+{
+    return (int)((uint64_t)__double_as_longlong(d2) >> 50);
+}
+__device__ __forceinline__ int d2_code16(double d2)
+{
+    return (int)((uint64_t)__double_as_longlong(d2) >> 48);
+}
+
+constexpr int kSeedBins = 176;  // quarter octaves: d^2 = 0 and [1, 2^43)
+constexpr int kSeedBase = 4088; // code4 of d^2 = 1 is 4092 (bin 4)
+constexpr int kMainBins = 64;   // quarter octaves below the bound S (16 octaves)
+
+// Per-lane packed 16-bit histogram in LDS: word w of lane l at h[w*64 + l].
+// Adds `one` (0 or 1) to the bin; the add is unconditional so that loops
+// stay free of branches and their LDS reads can be issued ahead.
+__device__ __forceinline__ void hist_add(uint32_t *h, int lane, int bin, uint32_t one)
+{
+    atomicAdd(&h[(bin >> 1) * 64 + lane], one << ((bin & 1) << 4));
+}
+
+// First bin where the running count reaches `need`; *below* = count before it.
+// Returns nbins when the total stays short.
+__device__ __forceinline__ int hist_find(const uint32_t *h, int lane, int nbins, int need, int *below)
+{
+    int cum = 0;
+    for (int w = 0; w < (nbins >> 1); w++) {
+        const uint32_t v = h[w * 64 + lane];
+        const int lo = (int)(v & 0xffffu), hi = (int)(v >> 16);
+        if (cum + lo >= need) {
+            *below = cum;
+            return 2 * w;
+        }
+        cum += lo;
+        if (cum + hi >= need) {
+            *below = cum;
+            return 2 * w + 1;
+        }
+        cum += hi;
+    }
+    *below = cum;
+    return nbins;
+}
+
+// 4-ary max-heap over slots [base, base + size) of one lane.
+__device__ __forceinline__ void subheap_sift(uint64_t *heap, int lane, int base, int size, int i,
+                                             uint64_t x)
+{
+    for (;;) {
+        const int c = 4 * i + 1;
+        if (c >= size) break;
+        int m = c;
+        uint64_t v = heap[(base + c) * 64 + lane];
+#pragma unroll
+        for (int d = 1; d < 4; d++) {
+            if (c + d < size) {
+                const uint64_t w = heap[(base + c + d) * 64 + lane];
+                if (w > v) {
+                    v = w;
+                    m = c + d;
+                }
+            }
+        }
+        if (v <= x) break;
+        heap[(base + i) * 64 + lane] = v;
+        i = m;
+    }
+    heap[(base + i) * 64 + lane] = x;
+}
+
+// One wave per block and per SIMD (the LDS heap decides occupancy), so the
+// compiler may spend registers on keeping LDS reads in flight.
+template <bool PERIODIC, bool IDS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_density(KnnArgs a)
+{
+    // the heap area doubles as the per-lane histograms of the selection
+    __shared__ uint64_t heap[kHeapSlots * 64];
     __shared__ SortedRec stage[64];
-    __shared__ uint32_t stk[64];
+    __shared__ uint32_t leaves[kLeafList];
+    uint32_t *hist = reinterpret_cast<uint32_t *>(heap);
+    // the walk's two frontier buffers also live in the heap area
+    uint32_t *front_a = reinterpret_cast<uint32_t *>(heap);
+    uint32_t *front_b = front_a + kFrontLevel;
 
     const int lane = threadIdx.x;
     // XCD-aware bucket order: consecutive blocks land on different XCDs, so
@@ -228,156 +354,352 @@ __global__ __launch_bounds__(64) void k_knn_density(KnnArgs a)
     const int bcount = (int)min((int64_t)HOP_BUCKET, a.n - b0);
     const bool active = lane < bcount;
     const int hs = a.hs;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const double G = a.gsize;
 
-    // stage the bucket's own particles
     if (active) stage[lane] = a.recs[b0 + lane];
+    for (int w = 0; w < kSeedBins / 2; w++) hist[w * 64 + lane] = 0u;
     __syncthreads();
     const SortedRec me = stage[active ? lane : 0];
     const double qx = me.x, qy = me.y, qz = me.z;
     const uint32_t ux = (uint32_t)qx, uy = (uint32_t)qy, uz = (uint32_t)qz;
+    const int32_t mytk = me.tk;
 
-    // initial heap: the bucket's other particles (first hs of them heapified,
-    // the rest offered)
+    // 1. bound: a quarter-octave histogram of d^2 over the bucket and two
+    //    Morton-neighbour buckets on each side; S = upper edge of the bin
+    //    holding the hs-th smallest, so S > (hs-th neighbour distance)^2
+    for (int side = 0; side < 5; side++) {
+        const int64_t nb0 = b0 + (side - 2) * HOP_BUCKET;
+        if (nb0 < 0 || nb0 >= a.n) continue;
+        const int ncnt = (int)min((int64_t)HOP_BUCKET, a.n - nb0);
+        if (side != 2) {
+            __syncthreads();
+            if (lane < ncnt) stage[lane] = a.recs[nb0 + lane];
+            __syncthreads();
+        }
+        for (int k0 = 0; k0 < HOP_BUCKET; k0 += 16) {
+            // all reads of a group before its histogram updates, so that the
+            // reads are not held behind the LDS atomics
+            int bin[16];
+            uint32_t one[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const SortedRec p = stage[k0 + k];
+                const double d2 = PERIODIC ? d2_wrap(qx, qy, qz, p, G) : d2_direct(qx, qy, qz, p);
+                one[k] = (k0 + k < ncnt && p.tk != mytk) ? 1u : 0u;
+                bin[k] = min(max(d2_code4(d2) - kSeedBase, 0), kSeedBins - 1);
+            }
+#pragma unroll
+            for (int k = 0; k < 16; k++) hist_add(hist, lane, bin[k], one[k]);
+        }
+    }
+    double S;
     {
-        int filled = 0;
+        int below;
+        const int b = hist_find(hist, lane, kSeedBins, hs, &below);
+        S = b < kSeedBins ? __longlong_as_double((long long)((uint64_t)(b + kSeedBase + 1) << 50))
+                          : 1.0e300;
+    }
+    double tmax = active ? S : 0.0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, d));
+
+    // groups of 8 consecutive lanes: box of their queries and largest bound,
+    // held in scalar registers for the walk
+    NodeBox gbox[8];
+    double gt[8];
+    {
+        uint32_t lo[3] = {active ? ux : 0xffffffffu, active ? uy : 0xffffffffu, active ? uz : 0xffffffffu};
+        uint32_t hi[3] = {active ? ux : 0u, active ? uy : 0u, active ? uz : 0u};
+        double t = active ? S : -1.0;
+#pragma unroll
+        for (int d = 1; d < 8; d <<= 1) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                lo[k] = min(lo[k], (uint32_t)__shfl_xor((int)lo[k], d));
+                hi[k] = max(hi[k], (uint32_t)__shfl_xor((int)hi[k], d));
+            }
+            t = fmax(t, __shfl_xor(t, d));
+        }
+#pragma unroll
+        for (int g = 0; g < 8; g++) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                gbox[g].lo[k] = (uint32_t)__builtin_amdgcn_readlane((int)lo[k], 8 * g);
+                gbox[g].hi[k] = (uint32_t)__builtin_amdgcn_readlane((int)hi[k], 8 * g);
+            }
+            const long long tb = __double_as_longlong(t);
+            const int tlo = __builtin_amdgcn_readlane((int)(tb & 0xffffffff), 8 * g);
+            const int thi = __builtin_amdgcn_readlane((int)(tb >> 32), 8 * g);
+            gt[g] = __longlong_as_double(((long long)thi << 32) | (uint32_t)tlo);
+        }
+    }
+
+    // 2. breadth-first walk: keep the nodes within a group's bound of that
+    //    group's box; 64 lanes test 64 children at once
+    const NodeBox bb = a.boxes[a.lv.off[2] + bucket];
+    unsigned long long n_nodes = 0, n_lv = 0;
+    int fcnt = 1;
+    bool overflow = tmax >= 1.0e299;
+    uint32_t *fc = front_a, *fn = front_b;
+    fc[0] = 0;
+    __syncthreads();
+    for (int h = a.lv.top; h > 0 && !overflow; h--) {
+        const int cap = min(a.front_cap, h == 1 ? kLeafList : kFrontLevel);
+        int ncnt = 0;
+        for (int base = 0; base < fcnt; base += 32) {
+            const int ni = base + (lane >> 1);
+            bool need = false;
+            uint32_t child = 0;
+            if (ni < fcnt) {
+                child = 2 * fc[ni] + (uint32_t)(lane & 1);
+                if (child < (uint32_t)a.lv.cnt[h - 1]) {
+                    const NodeBox cb = a.boxes[a.lv.off[h - 1] + child];
+#pragma unroll
+                    for (int g = 0; g < 8; g++) need |= boxbox_d2<PERIODIC>(gbox[g], cb, a.gmask) <= gt[g];
+                }
+            }
+            const uint64_t m = __ballot(need);
+            const int pos = ncnt + (int)__popcll(m & lt_mask);
+            if (need && pos < cap) fn[pos] = child;
+            ncnt += (int)__popcll(m);
+            n_nodes += 64;
+        }
+        __syncthreads();
+        if (ncnt > cap) {
+            overflow = true;
+            break;
+        }
+        uint32_t *t = fc;
+        fc = fn;
+        fn = t;
+        fcnt = ncnt;
+    }
+    if (!overflow) {
+        for (int i = lane; i < fcnt; i += 64) leaves[i] = fc[i];
+        __syncthreads();
+    }
+
+    if (!overflow) {
+        // 3. stream the surviving leaves, 4 leaves (64 particles) per batch,
+        //    loading batch b+1 while batch b is tested.  When every relevant
+        //    separation stays under half the box, the loading lane moves each
+        //    particle to its image nearest the bucket centre, so the testing
+        //    lanes need no per-pair wrap.
+        bool fastB = true;
+        double cx = 0, cy = 0, cz = 0;
+        if (PERIODIC) {
+            const double r = __builtin_sqrt(tmax);
+            const double half = 0.5 * G;
+#pragma unroll
+            for (int k = 0; k < 3; k++)
+                if ((double)(bb.hi[k] - bb.lo[k]) + 2.0 * r + 2.0 >= half) fastB = false;
+            cx = 0.5 * ((double)bb.lo[0] + (double)bb.hi[0]);
+            cy = 0.5 * ((double)bb.lo[1] + (double)bb.hi[1]);
+            cz = 0.5 * ((double)bb.lo[2] + (double)bb.hi[2]);
+        }
+        const int nbatch = (fcnt + 3) >> 2;
+        auto fetch = [&](int bi, SortedRec &r) -> bool {
+            const int li = 4 * bi + (lane >> 4);
+            if (li >= fcnt) return false;
+            const int64_t idx = (int64_t)leaves[li] * HOP_LEAF + (lane & 15);
+            if (idx >= a.n) return false;
+            r = a.recs[idx];
+            return true;
+        };
+        // one pass over the frontier; body(st) sees one staged batch
+        auto stream = [&](auto body) {
+            SortedRec nxt;
+            bool nxt_ok = nbatch > 0 ? fetch(0, nxt) : false;
+            for (int bi = 0; bi < nbatch; bi++) {
+                SortedRec r = nxt;
+                const bool ok = nxt_ok;
+                if (ok) {
+                    if (PERIODIC && fastB) {
+                        const double half = 0.5 * G;
+                        const double dx = r.x - cx, dy = r.y - cy, dz = r.z - cz;
+                        r.x += dx > half ? -G : (dx < -half ? G : 0.0);
+                        r.y += dy > half ? -G : (dy < -half ? G : 0.0);
+                        r.z += dz > half ? -G : (dz < -half ? G : 0.0);
+                    }
+                } else {
+                    r.x = r.y = r.z = 1.0e30;  // never selected
+                    r.j = -1;
+                    r.tk = -1;
+                }
+                __syncthreads();
+                stage[lane] = r;
+                __syncthreads();
+                if (bi + 1 < nbatch) nxt_ok = fetch(bi + 1, nxt);
+                if (__any(ok)) body();
+            }
+        };
+        auto dist = [&](const SortedRec &p) -> double {
+            return (!PERIODIC || fastB) ? d2_direct(qx, qy, qz, p) : d2_wrap(qx, qy, qz, p, G);
+        };
+        const int base4 = d2_code4(S) - kMainBins;
+
+        // 4. histogram pass: quarter-octave bins of d^2 below S
+        for (int w = 0; w < kMainBins / 2; w++) hist[w * 64 + lane] = 0u;
+        stream([&]() {
+            n_lv += 4;
+            for (int k0 = 0; k0 < 64; k0 += 16) {
+                int bin[16];
+                uint32_t one[16];
+                SortedRec pr[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) pr[k] = stage[k0 + k];
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    const SortedRec &p = pr[k];
+                    const int b = d2_code4(dist(p)) - base4;
+                    one[k] = (b < kMainBins && p.tk != mytk) ? 1u : 0u;
+                    bin[k] = min(max(b, 0), kMainBins - 1);
+                }
+#pragma unroll
+                for (int k = 0; k < 16; k++) hist_add(hist, lane, bin[k], one[k]);
+            }
+        });
+        int c_lo = 0;
+        const int bstar = hist_find(hist, lane, kMainBins, hs, &c_lo);
+        // slots [0, c_lo) take the particles below bin b*; slots [c_lo, hs)
+        // hold a max-heap of the smallest ones inside bin b*
+        const int rsz = hs - c_lo;
+        for (int s = 0; s < kHeapSlots; s++) heap[s * 64 + lane] = ~0ull;
+
+        // 5. collection pass
+        int nc = 0, nb = 0;
+        stream([&]() {
+            // branch-free selection mask first, then the few selected
+            uint64_t sel = 0;
+            for (int k0 = 0; k0 < 64; k0 += 16) {
+                SortedRec pr[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) pr[k] = stage[k0 + k];
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    const int b = min(max(d2_code4(dist(pr[k])) - base4, 0), kMainBins);
+                    sel |= (uint64_t)((b <= bstar && pr[k].tk != mytk) ? 1u : 0u) << (k0 + k);
+                }
+            }
+            while (__any(sel != 0)) {
+                if (sel != 0) {
+                    const int k = __builtin_ctzll(sel);
+                    sel &= sel - 1;
+                    const SortedRec p = stage[k];
+                    const double d2 = dist(p);
+                    const int b = min(max(d2_code4(d2) - base4, 0), kMainBins);
+                    const uint64_t key = make_key(d2, (uint32_t)p.tk, a);
+                    if (b < bstar) {
+                        heap[nc * 64 + lane] = key;
+                        nc++;
+                    } else if (nb < rsz) {
+                        heap[(c_lo + nb) * 64 + lane] = key;
+                        nb++;
+                        if (nb == rsz)
+                            for (int i = (rsz - 2) / 4; i >= 0; i--)
+                                subheap_sift(heap, lane, c_lo, rsz, i, heap[(c_lo + i) * 64 + lane]);
+                    } else if (key < heap[c_lo * 64 + lane]) {
+                        subheap_sift(heap, lane, c_lo, rsz, 0, key);
+                    }
+                }
+            }
+        });
+    } else {
+        // exact depth-first walk, nearest child first, with per-leaf heap
+        // insertion, for buckets whose bound covers too much of the tree
+        for (int s = 0; s < kHeapSlots; s++) heap[s * 64 + lane] = 0;
+        __syncthreads();
+        if (active) stage[lane] = a.recs[b0 + lane];
+        __syncthreads();
+        int slot = 0;
         for (int k = 0; k < HOP_BUCKET; k++) {
-            if (k == lane) continue;  // divergent only for this lane's own slot
+            if (k == lane) continue;
             uint64_t key = ~0ull;
             if (k < bcount) {
-                double d2 = pair_d2<PERIODIC>(qx, qy, qz, stage[k], false, a.gsize);
+                const double d2 = PERIODIC ? d2_wrap(qx, qy, qz, stage[k], G) : d2_direct(qx, qy, qz, stage[k]);
                 key = make_key(d2, (uint32_t)stage[k].tk, a);
             }
-            if (filled < hs) {
-                heap[filled * 64 + lane] = key;
-                filled++;
-                if (filled == hs) {
-                    for (int i = hs / 2 - 1; i >= 0; i--) heap_sift(heap, lane, hs, i, heap[i * 64 + lane]);
-                }
+            if (slot < hs) {
+                heap[slot * 64 + lane] = key;
+                slot++;
+                if (slot == hs)
+                    for (int i = (hs - 2) / 4; i >= 0; i--) heap_sift(heap, lane, hs, i, heap[i * 64 + lane]);
             } else if (key < heap[lane]) {
                 heap_sift(heap, lane, hs, 0, key);
             }
         }
-        if (filled < hs) {  // only when the bucket is smaller than hs + 1
-            for (int s = filled; s < hs; s++) heap[s * 64 + lane] = ~0ull;
-            for (int i = hs / 2 - 1; i >= 0; i--) heap_sift(heap, lane, hs, i, heap[i * 64 + lane]);
-        }
-    }
-    uint64_t tau_key = heap[lane];
-    double tau = active ? (double)(tau_key >> a.shift) : -1.0;
-
-    // bucket box (level-2 node = the bucket's 4 leaves) for near-first order
-    // and for the periodic fast path
-    const NodeBox bb = a.boxes[a.lv.off[2] + bucket];
-    const int64_t bcx = ((int64_t)bb.lo[0] + bb.hi[0]) >> 1;
-    const int64_t bcy = ((int64_t)bb.lo[1] + bb.hi[1]) >> 1;
-    const int64_t bcz = ((int64_t)bb.lo[2] + bb.hi[2]) >> 1;
-    const int64_t G = (int64_t)a.gmask + 1;
-
-    unsigned long long n_nodes = 0, n_leaves = 0;
-    int sp = 0;
-    stk[sp++] = ((uint32_t)a.lv.top << 27) | 0u;
-    while (sp > 0) {
-        const uint32_t code = __builtin_amdgcn_readfirstlane(stk[--sp]);
-        const int h = (int)(code >> 27);
-        const int64_t j = code & ((1u << 27) - 1);
-        const NodeBox bx = a.boxes[a.lv.off[h] + j];
-        n_nodes++;
-        double gx = axis_gap<PERIODIC>(ux, bx.lo[0], bx.hi[0], a.gmask);
-        double gy = axis_gap<PERIODIC>(uy, bx.lo[1], bx.hi[1], a.gmask);
-        double gz = axis_gap<PERIODIC>(uz, bx.lo[2], bx.hi[2], a.gmask);
-        double md2 = __builtin_fma(gx, gx, __builtin_fma(gy, gy, gz * gz));
-        if (!__any(md2 <= tau)) continue;
-        if (h > 0) {
-            const int64_t c0 = 2 * j, c1 = 2 * j + 1;
-            if (c1 >= a.lv.cnt[h - 1]) {
-                stk[sp++] = ((uint32_t)(h - 1) << 27) | (uint32_t)c0;
+        uint64_t tau_key = heap[lane];
+        double tau = active ? key_d2(tau_key, a.shift) : -1.0;
+        const int mid = bcount >> 1;
+        uint32_t *stk = leaves;
+        int sp = 0;
+        __syncthreads();
+        stk[sp++] = ((uint32_t)a.lv.top << 27) | 0u;
+        while (sp > 0) {
+            const uint32_t code = __builtin_amdgcn_readfirstlane(stk[--sp]);
+            const int h = (int)(code >> 27);
+            const int64_t j = code & ((1u << 27) - 1);
+            if (h > 0) {
+                const int64_t c0 = 2 * j, c1 = 2 * j + 1;
+                const bool has1 = c1 < a.lv.cnt[h - 1];
+                const NodeBox b0x = a.boxes[a.lv.off[h - 1] + c0];
+                const double md0 = box_d2<PERIODIC>(ux, uy, uz, b0x, a.gmask);
+                const bool need0 = __any(md0 <= tau);
+                bool need1 = false;
+                double md1 = 0.0;
+                if (has1) {
+                    const NodeBox b1x = a.boxes[a.lv.off[h - 1] + c1];
+                    md1 = box_d2<PERIODIC>(ux, uy, uz, b1x, a.gmask);
+                    need1 = __any(md1 <= tau);
+                }
+                n_nodes += 1 + (has1 ? 1 : 0);
+                const uint32_t k0 = ((uint32_t)(h - 1) << 27) | (uint32_t)c0;
+                const uint32_t k1 = ((uint32_t)(h - 1) << 27) | (uint32_t)c1;
+                const double r0 = __shfl(md0, mid), r1 = __shfl(md1, mid);
+                if (need0 && need1) {
+                    if (r0 <= r1) {
+                        stk[sp++] = k1;
+                        stk[sp++] = k0;
+                    } else {
+                        stk[sp++] = k0;
+                        stk[sp++] = k1;
+                    }
+                } else if (need0) {
+                    stk[sp++] = k0;
+                } else if (need1) {
+                    stk[sp++] = k1;
+                }
                 continue;
             }
-            // near-first: Chebyshev distance from the bucket centre to each
-            // child's centre (minimum image when periodic)
-            const NodeBox b0x = a.boxes[a.lv.off[h - 1] + c0];
-            const NodeBox b1x = a.boxes[a.lv.off[h - 1] + c1];
-            int64_t d0 = 0, d1 = 0;
-            const int64_t bc[3] = {bcx, bcy, bcz};
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                int64_t e0 = ((((int64_t)b0x.lo[k] + b0x.hi[k]) >> 1) - bc[k]);
-                int64_t e1 = ((((int64_t)b1x.lo[k] + b1x.hi[k]) >> 1) - bc[k]);
-                e0 = e0 < 0 ? -e0 : e0;
-                e1 = e1 < 0 ? -e1 : e1;
-                if (PERIODIC) {
-                    e0 = min(e0, G - e0);
-                    e1 = min(e1, G - e1);
-                }
-                d0 = max(d0, e0);
-                d1 = max(d1, e1);
+            if ((j >> 2) == bucket) continue;  // the bucket's own leaves are in the heap
+            const NodeBox bx = a.boxes[j];
+            if (!__any(box_d2<PERIODIC>(ux, uy, uz, bx, a.gmask) <= tau)) continue;
+            n_lv++;
+            const int cnt = (int)bx.count;
+            __syncthreads();
+            if (lane < cnt * 4) {
+                const uint64_t *src = reinterpret_cast<const uint64_t *>(a.recs + j * HOP_LEAF);
+                reinterpret_cast<uint64_t *>(stage)[lane] = src[lane];
             }
-            const uint32_t k0 = ((uint32_t)(h - 1) << 27) | (uint32_t)c0;
-            const uint32_t k1 = ((uint32_t)(h - 1) << 27) | (uint32_t)c1;
-            if (d0 <= d1) {
-                stk[sp++] = k1;
-                stk[sp++] = k0;
-            } else {
-                stk[sp++] = k0;
-                stk[sp++] = k1;
+            __syncthreads();
+            uint32_t pass = 0;
+            for (int k = 0; k < cnt; k++) {
+                const double d2 = PERIODIC ? d2_wrap(qx, qy, qz, stage[k], G) : d2_direct(qx, qy, qz, stage[k]);
+                pass |= (d2 <= tau ? 1u : 0u) << k;
             }
-            continue;
-        }
-        // a leaf
-        if ((j >> 2) == bucket) continue;  // the bucket's own leaves are in the heap
-        n_leaves++;
-        const int cnt = (int)bx.count;
-        const int64_t p0 = j * HOP_LEAF;
-        __syncthreads();
-        if (lane < cnt * 4) {
-            const uint64_t *src = reinterpret_cast<const uint64_t *>(a.recs + p0);
-            reinterpret_cast<uint64_t *>(stage)[lane] = src[lane];
-        }
-        __syncthreads();
-        // periodic fast path: one image shift per axis for the whole leaf when
-        // every query-particle separation stays within half the box
-        bool fast = true;
-        double sx = 0, sy = 0, sz = 0;
-        if (PERIODIC) {
-            const int64_t half = G >> 1;
-            double sh[3];
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                int64_t lc = ((int64_t)bx.lo[k] + bx.hi[k]) >> 1;
-                int64_t s = 0;
-                if (lc - ((k == 0) ? bcx : (k == 1) ? bcy : bcz) > half) s = G;
-                if (lc - ((k == 0) ? bcx : (k == 1) ? bcy : bcz) < -half) s = -G;
-                // particle p is used as p - s; the largest separation
-                int64_t m1 = (int64_t)bb.hi[k] - ((int64_t)bx.lo[k] - s);
-                int64_t m2 = ((int64_t)bx.hi[k] - s) - (int64_t)bb.lo[k];
-                if (max(m1, m2) > half) fast = false;
-                sh[k] = (double)s;
-            }
-            sx = sh[0];
-            sy = sh[1];
-            sz = sh[2];
-        }
-        const double fx = qx + sx, fy = qy + sy, fz = qz + sz;
-        uint32_t pass = 0;
-        for (int k = 0; k < cnt; k++) {
-            const SortedRec p = stage[k];
-            double d2 = fast ? pair_d2<false>(fx, fy, fz, p, true, a.gsize)
-                             : pair_d2<PERIODIC>(qx, qy, qz, p, false, a.gsize);
-            pass |= (d2 <= tau ? 1u : 0u) << k;
-        }
-        // insert the passing particles, lane by lane
-        while (__any(pass != 0)) {
-            if (pass != 0) {
-                const int k = __builtin_ctz(pass);
-                pass &= pass - 1;
-                const SortedRec p = stage[k];
-                double d2 = fast ? pair_d2<false>(fx, fy, fz, p, true, a.gsize)
-                                 : pair_d2<PERIODIC>(qx, qy, qz, p, false, a.gsize);
-                uint64_t key = make_key(d2, (uint32_t)p.tk, a);
-                if (key < tau_key) {
-                    heap_sift(heap, lane, hs, 0, key);
-                    tau_key = heap[lane];
-                    tau = (double)(tau_key >> a.shift);
+            while (__any(pass != 0)) {
+                if (pass != 0) {
+                    const int k = __builtin_ctz(pass);
+                    pass &= pass - 1;
+                    const SortedRec p = stage[k];
+                    const double d2 = PERIODIC ? d2_wrap(qx, qy, qz, p, G) : d2_direct(qx, qy, qz, p);
+                    const uint64_t key = make_key(d2, (uint32_t)p.tk, a);
+                    if (key < tau_key) {
+                        heap_sift(heap, lane, hs, 0, key);
+                        tau_key = heap[lane];
+                        tau = key_d2(tau_key, a.shift);
+                    }
                 }
             }
         }
@@ -385,7 +707,7 @@ __global__ __launch_bounds__(64) void k_knn_density(KnnArgs a)
 
     if (a.counters && lane == 0) {
         atomicAdd(&a.counters[0], n_nodes);
-        atomicAdd(&a.counters[1], n_leaves);
+        atomicAdd(&a.counters[1], n_lv);
     }
     if (!active) return;
 
@@ -443,11 +765,11 @@ __global__ __launch_bounds__(64) void k_knn_density(KnnArgs a)
         }
         part[lvl] = s;
     }
-    const double S = part[6];
+    const double wsum = part[6];
     const double h2 = Rd * 0.25;
     const double hh = __builtin_sqrt(h2);
     const double h3 = h2 * hh;
-    const double delta = (S * a.norm) / h3;
+    const double delta = (wsum * a.norm) / h3;
 
     const int32_t jq = me.j;
     a.dens[jq] = delta;
@@ -568,6 +890,7 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     a.norm = 1.0 / (3.141592653589793 * md);
     a.gsize = (double)glim;
     a.gmask = glim - 1;
+    a.front_cap = std::min(std::max(ctx->front_cap, 1), kFront);
     a.vec_store = nbr && (p->k_store % 4 == 0) && (((uintptr_t)nbr & 15) == 0);
     a.nbr = nbr;
     a.dens = density;
@@ -603,7 +926,7 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
         ctx->stats.n = n;
         ctx->stats.nodes_visited = (int64_t)c[0];
         ctx->stats.leaves_scanned = (int64_t)c[1];
-        for (auto &e : ev) hipEventDestroy(e);
+        for (auto &e : ev) (void)hipEventDestroy(e);
     }
     return HOP_OK;
 }

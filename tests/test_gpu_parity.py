@@ -170,3 +170,23 @@ def test_degenerate_reported(ctx):
         gpu_run(ctx, synth.Particles(pos=pos, periodic=True, mean_density=200 / 2.0 ** 63),
                 _params(synth.Particles(pos=pos, periodic=True, mean_density=200 / 2.0 ** 63)))
     assert e.value.code == -3
+
+
+def test_depth_first_fallback_parity(orc, monkeypatch):
+    """A tiny frontier capacity sends every bucket to the exact depth-first
+    fallback walk; results must not change."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1001_3411_amd import HopContext
+    monkeypatch.setenv("HOP_FRONT_CAP", "2")
+    c = HopContext(0)
+    try:
+        for p in (synth.config(1), synth.padded_subvolume(9000, 41)):
+            pr = p.padded is not None
+            r = orc.run(p.pos, periodic=p.periodic, mean_density=p.mean_density,
+                        padded=p.padded, padded_rules=pr)
+            g = gpu_run(c, p, _params(p, padded_rules=pr))
+            assert_parity(g, r, f"fallback-{p.name}")
+    finally:
+        c.close()
