@@ -256,90 +256,88 @@ __device__ __forceinline__ double boxbox_d2(const NodeBox &p, const NodeBox &q, 
     return g2;
 }
 
-// Codes for the radix selection: the top bits of an exact integer d^2 held
-// in a double (sign, 11 exponent bits, leading mantissa bits) grow with d^2.
-// code4 steps by a quarter octave, code16 by a sixteenth of an octave.
-__device__ __forceinline__ int d2_code4(double d2)
-{
-    return (int)((uint64_t)__double_as_longlong(d2) >> 50);
-}
-__device__ __forceinline__ int d2_code16(double d2)
-{
-    return (int)((uint64_t)__double_as_longlong(d2) >> 48);
-}
+// Per-lane 4-ary max-heap of hs keys.  The root (index 0) and its four
+// children (indices 1-4) live in registers, the deeper levels (indices
+// 5..hs-1) in LDS at heap[i*64 + lane]; LDS slots hs..64 hold 0 so that
+// missing children never win.  Replacing the root therefore costs two
+// dependent LDS round trips instead of one per level.
+struct RegHeap {
+    uint64_t r0;
+    uint64_t r1[4];
+};
 
-constexpr int kSeedBins = 176;  // quarter octaves: d^2 = 0 and [1, 2^43)
-constexpr int kSeedBase = 4088; // code4 of d^2 = 1 is 4092 (bin 4)
-constexpr int kMainBins = 64;   // quarter octaves below the bound S (16 octaves)
-
-// Per-lane packed 16-bit histogram in LDS: word w of lane l at h[w*64 + l].
-// Adds `one` (0 or 1) to the bin; the add is unconditional so that loops
-// stay free of branches and their LDS reads can be issued ahead.
-__device__ __forceinline__ void hist_add(uint32_t *h, int lane, int bin, uint32_t one)
-{
-    atomicAdd(&h[(bin >> 1) * 64 + lane], one << ((bin & 1) << 4));
-}
-
-// First bin where the running count reaches `need`; *below* = count before it.
-// Returns nbins when the total stays short.
-__device__ __forceinline__ int hist_find(const uint32_t *h, int lane, int nbins, int need, int *below)
-{
-    int cum = 0;
-    for (int w = 0; w < (nbins >> 1); w++) {
-        const uint32_t v = h[w * 64 + lane];
-        const int lo = (int)(v & 0xffffu), hi = (int)(v >> 16);
-        if (cum + lo >= need) {
-            *below = cum;
-            return 2 * w;
-        }
-        cum += lo;
-        if (cum + hi >= need) {
-            *below = cum;
-            return 2 * w + 1;
-        }
-        cum += hi;
-    }
-    *below = cum;
-    return nbins;
-}
-
-// 4-ary max-heap over slots [base, base + size) of one lane.
-__device__ __forceinline__ void subheap_sift(uint64_t *heap, int lane, int base, int size, int i,
-                                             uint64_t x)
+// LDS-only 4-ary sift of x from node i (i >= 1, children at 4i+1..4i+4).
+__device__ __forceinline__ void lds_sift(uint64_t *heap, int lane, int hs, int i, uint64_t x)
 {
     for (;;) {
         const int c = 4 * i + 1;
-        if (c >= size) break;
-        int m = c;
-        uint64_t v = heap[(base + c) * 64 + lane];
-#pragma unroll
-        for (int d = 1; d < 4; d++) {
-            if (c + d < size) {
-                const uint64_t w = heap[(base + c + d) * 64 + lane];
-                if (w > v) {
-                    v = w;
-                    m = c + d;
-                }
-            }
-        }
+        if (c >= hs) break;
+        const uint64_t k0 = heap[c * 64 + lane], k1 = heap[(c + 1) * 64 + lane];
+        const uint64_t k2 = heap[(c + 2) * 64 + lane], k3 = heap[(c + 3) * 64 + lane];
+        const int m01 = k1 > k0 ? c + 1 : c;
+        const uint64_t v01 = k1 > k0 ? k1 : k0;
+        const int m23 = k3 > k2 ? c + 3 : c + 2;
+        const uint64_t v23 = k3 > k2 ? k3 : k2;
+        const int m = v23 > v01 ? m23 : m01;
+        const uint64_t v = v23 > v01 ? v23 : v01;
         if (v <= x) break;
-        heap[(base + i) * 64 + lane] = v;
+        heap[i * 64 + lane] = v;
         i = m;
     }
-    heap[(base + i) * 64 + lane] = x;
+    heap[i * 64 + lane] = x;
 }
 
-// One wave per block and per SIMD (the LDS heap decides occupancy), so the
-// compiler may spend registers on keeping LDS reads in flight.
+// Replace the root by x (x below the root) and restore the heap.  Levels 0
+// and 1 are registers (selected without indexing), deeper levels LDS.
+__device__ __forceinline__ void rh_replace_root(RegHeap &H, uint64_t *heap, int lane, int hs, uint64_t x)
+{
+    if (hs <= 1) {
+        H.r0 = x;
+        return;
+    }
+    const uint64_t k0 = H.r1[0], k1 = H.r1[1], k2 = H.r1[2], k3 = H.r1[3];
+    const int m01 = k1 > k0 ? 1 : 0;
+    const uint64_t v01 = k1 > k0 ? k1 : k0;
+    const int m23 = k3 > k2 ? 3 : 2;
+    const uint64_t v23 = k3 > k2 ? k3 : k2;
+    const int m = v23 > v01 ? m23 : m01;  // child 1+m
+    const uint64_t v = v23 > v01 ? v23 : v01;
+    if (v <= x) {
+        H.r0 = x;
+        return;
+    }
+    H.r0 = v;
+    // x moves into child 1+m unless one of that child's children is larger
+    const int c = 4 * (1 + m) + 1;
+    uint64_t put = x;
+    int deeper = -1;
+    if (c < hs) {
+        const uint64_t w0 = heap[c * 64 + lane], w1 = heap[(c + 1) * 64 + lane];
+        const uint64_t w2 = heap[(c + 2) * 64 + lane], w3 = heap[(c + 3) * 64 + lane];
+        const int n01 = w1 > w0 ? c + 1 : c;
+        const uint64_t u01 = w1 > w0 ? w1 : w0;
+        const int n23 = w3 > w2 ? c + 3 : c + 2;
+        const uint64_t u23 = w3 > w2 ? w3 : w2;
+        const int nm = u23 > u01 ? n23 : n01;
+        const uint64_t u = u23 > u01 ? u23 : u01;
+        if (u > x) {
+            put = u;
+            deeper = nm;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) H.r1[q] = (q == m) ? put : H.r1[q];
+    if (deeper >= 0) lds_sift(heap, lane, hs, deeper, x);
+}
+
 template <bool PERIODIC, bool IDS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_density(KnnArgs a)
 {
-    // the heap area doubles as the per-lane histograms of the selection
     __shared__ uint64_t heap[kHeapSlots * 64];
     __shared__ SortedRec stage[64];
     __shared__ uint32_t leaves[kLeafList];
-    uint32_t *hist = reinterpret_cast<uint32_t *>(heap);
-    // the walk's two frontier buffers also live in the heap area
+    // the walk's two frontier buffers live in the heap area until the heap
+    // is filled
     uint32_t *front_a = reinterpret_cast<uint32_t *>(heap);
     uint32_t *front_b = front_a + kFrontLevel;
 
@@ -356,51 +354,88 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     const int hs = a.hs;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const double G = a.gsize;
+    const int64_t n_leaf_total = a.lv.cnt[0];
+    unsigned long long n_nodes = 0, n_lv = 0;
 
     if (active) stage[lane] = a.recs[b0 + lane];
-    for (int w = 0; w < kSeedBins / 2; w++) hist[w * 64 + lane] = 0u;
     __syncthreads();
     const SortedRec me = stage[active ? lane : 0];
     const double qx = me.x, qy = me.y, qz = me.z;
     const uint32_t ux = (uint32_t)qx, uy = (uint32_t)qy, uz = (uint32_t)qz;
     const int32_t mytk = me.tk;
 
-    // 1. bound: a quarter-octave histogram of d^2 over the bucket and two
-    //    Morton-neighbour buckets on each side; S = upper edge of the bin
-    //    holding the hs-th smallest, so S > (hs-th neighbour distance)^2
+    // 1. seed the heap with the bucket's other particles (the first hs go
+    //    straight into place, then one heapify) ...
+    RegHeap H;
+    {
+        for (int s = 0; s < kHeapSlots; s++) heap[s * 64 + lane] = 0;
+        int slot = 0;
+        for (int k = 0; k < HOP_BUCKET && slot < hs; k++) {
+            if (k == lane) continue;
+            uint64_t key = ~0ull;
+            if (k < bcount) {
+                const double d2 = PERIODIC ? d2_wrap(qx, qy, qz, stage[k], G) : d2_direct(qx, qy, qz, stage[k]);
+                key = make_key(d2, (uint32_t)stage[k].tk, a);
+            }
+            heap[slot * 64 + lane] = key;
+            slot++;
+        }
+        for (int s = slot; s < hs; s++) heap[s * 64 + lane] = ~0ull;  // buckets smaller than hs + 1
+        for (int i = (hs - 2) / 4; i >= 0; i--) heap_sift(heap, lane, hs, i, heap[i * 64 + lane]);
+        H.r0 = heap[lane];
+#pragma unroll
+        for (int q = 0; q < 4; q++) H.r1[q] = heap[(q + 1) * 64 + lane];
+    }
+    uint64_t tau_key = H.r0;
+    double tau = active ? key_d2(tau_key, a.shift) : -1.0;
+    // offer the particles of the staged batch whose bits are set
+    auto insert_marked = [&](uint64_t pass, bool wrap) {
+        while (__any(pass != 0)) {
+            if (pass != 0) {
+                const int k = __builtin_ctzll(pass);
+                pass &= pass - 1;
+                const SortedRec p = stage[k];
+                const double d2 = wrap ? d2_wrap(qx, qy, qz, p, G) : d2_direct(qx, qy, qz, p);
+                const uint64_t key = make_key(d2, (uint32_t)p.tk, a);
+                if (key < tau_key) {
+                    rh_replace_root(H, heap, lane, hs, key);
+                    tau_key = H.r0;
+                    tau = key_d2(tau_key, a.shift);
+                }
+            }
+        }
+    };
+    // ... and offer the rest of the bucket (hs < 63 only) and two
+    //    Morton-neighbour buckets on each side (exact minimum image)
     for (int side = 0; side < 5; side++) {
         const int64_t nb0 = b0 + (side - 2) * HOP_BUCKET;
         if (nb0 < 0 || nb0 >= a.n) continue;
         const int ncnt = (int)min((int64_t)HOP_BUCKET, a.n - nb0);
-        if (side != 2) {
-            __syncthreads();
-            if (lane < ncnt) stage[lane] = a.recs[nb0 + lane];
-            __syncthreads();
-        }
+        if (side == 2 && hs >= HOP_BUCKET - 1) continue;
+        __syncthreads();
+        if (lane < ncnt) stage[lane] = a.recs[nb0 + lane];
+        __syncthreads();
+        uint64_t pass = 0;
         for (int k0 = 0; k0 < HOP_BUCKET; k0 += 16) {
-            // all reads of a group before its histogram updates, so that the
-            // reads are not held behind the LDS atomics
-            int bin[16];
-            uint32_t one[16];
+            SortedRec pr[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) pr[k] = stage[k0 + k];
 #pragma unroll
             for (int k = 0; k < 16; k++) {
-                const SortedRec p = stage[k0 + k];
-                const double d2 = PERIODIC ? d2_wrap(qx, qy, qz, p, G) : d2_direct(qx, qy, qz, p);
-                one[k] = (k0 + k < ncnt && p.tk != mytk) ? 1u : 0u;
-                bin[k] = min(max(d2_code4(d2) - kSeedBase, 0), kSeedBins - 1);
+                const int kk = k0 + k;
+                const double d2 = PERIODIC ? d2_wrap(qx, qy, qz, pr[k], G) : d2_direct(qx, qy, qz, pr[k]);
+                // own bucket: only the particles the fill did not take
+                const bool fresh = side != 2 || (kk != lane && kk - (kk > lane ? 1 : 0) >= hs);
+                pass |= (uint64_t)((kk < ncnt && fresh && pr[k].tk != mytk && d2 <= tau) ? 1u : 0u) << kk;
             }
-#pragma unroll
-            for (int k = 0; k < 16; k++) hist_add(hist, lane, bin[k], one[k]);
         }
+        insert_marked(pass, PERIODIC);
     }
-    double S;
-    {
-        int below;
-        const int b = hist_find(hist, lane, kSeedBins, hs, &below);
-        S = b < kSeedBins ? __longlong_as_double((long long)((uint64_t)(b + kSeedBase + 1) << 50))
-                          : 1.0e300;
-    }
-    double tmax = active ? S : 0.0;
+    // leaves whose particles have all been offered
+    const int64_t done_lo = max((int64_t)0, 4 * (bucket - 2));
+    const int64_t done_hi = min(n_leaf_total, 4 * (bucket + 3));
+
+    double tmax = tau;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, d));
 
@@ -411,7 +446,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     {
         uint32_t lo[3] = {active ? ux : 0xffffffffu, active ? uy : 0xffffffffu, active ? uz : 0xffffffffu};
         uint32_t hi[3] = {active ? ux : 0u, active ? uy : 0u, active ? uz : 0u};
-        double t = active ? S : -1.0;
+        double t = tau;
 #pragma unroll
         for (int d = 1; d < 8; d <<= 1) {
 #pragma unroll
@@ -436,16 +471,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     }
 
     // 2. breadth-first walk: keep the nodes within a group's bound of that
-    //    group's box; 64 lanes test 64 children at once
+    //    group's box; 64 lanes test 64 children at once.  The frontier uses
+    //    the heap's LDS levels, so levels 2-3 of the heap are parked in the
+    //    leaf list meanwhile.
     const NodeBox bb = a.boxes[a.lv.off[2] + bucket];
-    unsigned long long n_nodes = 0, n_lv = 0;
-    int fcnt = 1;
-    bool overflow = tmax >= 1.0e299;
+    // park heap levels 2..3 (slots 5..hs-1) in registers
+    uint64_t park[kHeapMax - 5];
+#pragma unroll
+    for (int s = 5; s < kHeapMax; s++) park[s - 5] = s < hs ? heap[s * 64 + lane] : 0;
+    __syncthreads();
+    int fcnt = 1, hf = a.lv.top;
     uint32_t *fc = front_a, *fn = front_b;
     fc[0] = 0;
     __syncthreads();
-    for (int h = a.lv.top; h > 0 && !overflow; h--) {
-        const int cap = min(a.front_cap, h == 1 ? kLeafList : kFrontLevel);
+    while (hf > 0) {
+        const int h = hf;
         int ncnt = 0;
         for (int base = 0; base < fcnt; base += 32) {
             const int ni = base + (lane >> 1);
@@ -461,249 +501,151 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
             }
             const uint64_t m = __ballot(need);
             const int pos = ncnt + (int)__popcll(m & lt_mask);
-            if (need && pos < cap) fn[pos] = child;
+            if (need && pos < kFrontLevel) fn[pos] = child;
             ncnt += (int)__popcll(m);
             n_nodes += 64;
         }
         __syncthreads();
-        if (ncnt > cap) {
-            overflow = true;
-            break;
-        }
+        if (ncnt > min(a.front_cap, kLeafList)) break;  // keep level h
         uint32_t *t = fc;
         fc = fn;
         fn = t;
         fcnt = ncnt;
+        hf = h - 1;
     }
-    if (!overflow) {
-        for (int i = lane; i < fcnt; i += 64) leaves[i] = fc[i];
-        __syncthreads();
-    }
-
-    if (!overflow) {
-        // 3. stream the surviving leaves, 4 leaves (64 particles) per batch,
-        //    loading batch b+1 while batch b is tested.  When every relevant
-        //    separation stays under half the box, the loading lane moves each
-        //    particle to its image nearest the bucket centre, so the testing
-        //    lanes need no per-pair wrap.
-        bool fastB = true;
-        double cx = 0, cy = 0, cz = 0;
-        if (PERIODIC) {
-            const double r = __builtin_sqrt(tmax);
-            const double half = 0.5 * G;
-#pragma unroll
-            for (int k = 0; k < 3; k++)
-                if ((double)(bb.hi[k] - bb.lo[k]) + 2.0 * r + 2.0 >= half) fastB = false;
-            cx = 0.5 * ((double)bb.lo[0] + (double)bb.hi[0]);
-            cy = 0.5 * ((double)bb.lo[1] + (double)bb.hi[1]);
-            cz = 0.5 * ((double)bb.lo[2] + (double)bb.hi[2]);
-        }
-        const int nbatch = (fcnt + 3) >> 2;
-        auto fetch = [&](int bi, SortedRec &r) -> bool {
-            const int li = 4 * bi + (lane >> 4);
-            if (li >= fcnt) return false;
-            const int64_t idx = (int64_t)leaves[li] * HOP_LEAF + (lane & 15);
-            if (idx >= a.n) return false;
-            r = a.recs[idx];
-            return true;
-        };
-        // one pass over the frontier; body(st) sees one staged batch
-        auto stream = [&](auto body) {
-            SortedRec nxt;
-            bool nxt_ok = nbatch > 0 ? fetch(0, nxt) : false;
-            for (int bi = 0; bi < nbatch; bi++) {
-                SortedRec r = nxt;
-                const bool ok = nxt_ok;
-                if (ok) {
-                    if (PERIODIC && fastB) {
-                        const double half = 0.5 * G;
-                        const double dx = r.x - cx, dy = r.y - cy, dz = r.z - cz;
-                        r.x += dx > half ? -G : (dx < -half ? G : 0.0);
-                        r.y += dy > half ? -G : (dy < -half ? G : 0.0);
-                        r.z += dz > half ? -G : (dz < -half ? G : 0.0);
-                    }
-                } else {
-                    r.x = r.y = r.z = 1.0e30;  // never selected
-                    r.j = -1;
-                    r.tk = -1;
+    // list of ranges (node | level << 27), leaves already offered removed,
+    // leaves overlapping the bucket box first
+    int lcnt = 0;
+    {
+        for (int pass = 0; pass < 2; pass++) {
+            for (int base = 0; base < fcnt; base += 64) {
+                const int i = base + lane;
+                bool keep = false;
+                uint32_t e = 0;
+                if (i < fcnt) {
+                    const uint32_t node = fc[i];
+                    e = node | ((uint32_t)hf << 27);
+                    const int64_t first = (int64_t)node << hf;
+                    const int64_t last = min(first + ((int64_t)1 << hf), n_leaf_total);
+                    const bool done = hf == 0 && first >= done_lo && last <= done_hi;
+                    const NodeBox nb = a.boxes[a.lv.off[hf] + node];
+                    const bool near = boxbox_d2<PERIODIC>(bb, nb, a.gmask) == 0.0;
+                    keep = !done && (pass == 0 ? near : !near);
                 }
-                __syncthreads();
-                stage[lane] = r;
-                __syncthreads();
-                if (bi + 1 < nbatch) nxt_ok = fetch(bi + 1, nxt);
-                if (__any(ok)) body();
-            }
-        };
-        auto dist = [&](const SortedRec &p) -> double {
-            return (!PERIODIC || fastB) ? d2_direct(qx, qy, qz, p) : d2_wrap(qx, qy, qz, p, G);
-        };
-        const int base4 = d2_code4(S) - kMainBins;
-
-        // 4. histogram pass: quarter-octave bins of d^2 below S
-        for (int w = 0; w < kMainBins / 2; w++) hist[w * 64 + lane] = 0u;
-        stream([&]() {
-            n_lv += 4;
-            for (int k0 = 0; k0 < 64; k0 += 16) {
-                int bin[16];
-                uint32_t one[16];
-                SortedRec pr[16];
-#pragma unroll
-                for (int k = 0; k < 16; k++) pr[k] = stage[k0 + k];
-#pragma unroll
-                for (int k = 0; k < 16; k++) {
-                    const SortedRec &p = pr[k];
-                    const int b = d2_code4(dist(p)) - base4;
-                    one[k] = (b < kMainBins && p.tk != mytk) ? 1u : 0u;
-                    bin[k] = min(max(b, 0), kMainBins - 1);
-                }
-#pragma unroll
-                for (int k = 0; k < 16; k++) hist_add(hist, lane, bin[k], one[k]);
-            }
-        });
-        int c_lo = 0;
-        const int bstar = hist_find(hist, lane, kMainBins, hs, &c_lo);
-        // slots [0, c_lo) take the particles below bin b*; slots [c_lo, hs)
-        // hold a max-heap of the smallest ones inside bin b*
-        const int rsz = hs - c_lo;
-        for (int s = 0; s < kHeapSlots; s++) heap[s * 64 + lane] = ~0ull;
-
-        // 5. collection pass
-        int nc = 0, nb = 0;
-        stream([&]() {
-            // branch-free selection mask first, then the few selected
-            uint64_t sel = 0;
-            for (int k0 = 0; k0 < 64; k0 += 16) {
-                SortedRec pr[16];
-#pragma unroll
-                for (int k = 0; k < 16; k++) pr[k] = stage[k0 + k];
-#pragma unroll
-                for (int k = 0; k < 16; k++) {
-                    const int b = min(max(d2_code4(dist(pr[k])) - base4, 0), kMainBins);
-                    sel |= (uint64_t)((b <= bstar && pr[k].tk != mytk) ? 1u : 0u) << (k0 + k);
-                }
-            }
-            while (__any(sel != 0)) {
-                if (sel != 0) {
-                    const int k = __builtin_ctzll(sel);
-                    sel &= sel - 1;
-                    const SortedRec p = stage[k];
-                    const double d2 = dist(p);
-                    const int b = min(max(d2_code4(d2) - base4, 0), kMainBins);
-                    const uint64_t key = make_key(d2, (uint32_t)p.tk, a);
-                    if (b < bstar) {
-                        heap[nc * 64 + lane] = key;
-                        nc++;
-                    } else if (nb < rsz) {
-                        heap[(c_lo + nb) * 64 + lane] = key;
-                        nb++;
-                        if (nb == rsz)
-                            for (int i = (rsz - 2) / 4; i >= 0; i--)
-                                subheap_sift(heap, lane, c_lo, rsz, i, heap[(c_lo + i) * 64 + lane]);
-                    } else if (key < heap[c_lo * 64 + lane]) {
-                        subheap_sift(heap, lane, c_lo, rsz, 0, key);
-                    }
-                }
-            }
-        });
-    } else {
-        // exact depth-first walk, nearest child first, with per-leaf heap
-        // insertion, for buckets whose bound covers too much of the tree
-        for (int s = 0; s < kHeapSlots; s++) heap[s * 64 + lane] = 0;
-        __syncthreads();
-        if (active) stage[lane] = a.recs[b0 + lane];
-        __syncthreads();
-        int slot = 0;
-        for (int k = 0; k < HOP_BUCKET; k++) {
-            if (k == lane) continue;
-            uint64_t key = ~0ull;
-            if (k < bcount) {
-                const double d2 = PERIODIC ? d2_wrap(qx, qy, qz, stage[k], G) : d2_direct(qx, qy, qz, stage[k]);
-                key = make_key(d2, (uint32_t)stage[k].tk, a);
-            }
-            if (slot < hs) {
-                heap[slot * 64 + lane] = key;
-                slot++;
-                if (slot == hs)
-                    for (int i = (hs - 2) / 4; i >= 0; i--) heap_sift(heap, lane, hs, i, heap[i * 64 + lane]);
-            } else if (key < heap[lane]) {
-                heap_sift(heap, lane, hs, 0, key);
-            }
-        }
-        uint64_t tau_key = heap[lane];
-        double tau = active ? key_d2(tau_key, a.shift) : -1.0;
-        const int mid = bcount >> 1;
-        uint32_t *stk = leaves;
-        int sp = 0;
-        __syncthreads();
-        stk[sp++] = ((uint32_t)a.lv.top << 27) | 0u;
-        while (sp > 0) {
-            const uint32_t code = __builtin_amdgcn_readfirstlane(stk[--sp]);
-            const int h = (int)(code >> 27);
-            const int64_t j = code & ((1u << 27) - 1);
-            if (h > 0) {
-                const int64_t c0 = 2 * j, c1 = 2 * j + 1;
-                const bool has1 = c1 < a.lv.cnt[h - 1];
-                const NodeBox b0x = a.boxes[a.lv.off[h - 1] + c0];
-                const double md0 = box_d2<PERIODIC>(ux, uy, uz, b0x, a.gmask);
-                const bool need0 = __any(md0 <= tau);
-                bool need1 = false;
-                double md1 = 0.0;
-                if (has1) {
-                    const NodeBox b1x = a.boxes[a.lv.off[h - 1] + c1];
-                    md1 = box_d2<PERIODIC>(ux, uy, uz, b1x, a.gmask);
-                    need1 = __any(md1 <= tau);
-                }
-                n_nodes += 1 + (has1 ? 1 : 0);
-                const uint32_t k0 = ((uint32_t)(h - 1) << 27) | (uint32_t)c0;
-                const uint32_t k1 = ((uint32_t)(h - 1) << 27) | (uint32_t)c1;
-                const double r0 = __shfl(md0, mid), r1 = __shfl(md1, mid);
-                if (need0 && need1) {
-                    if (r0 <= r1) {
-                        stk[sp++] = k1;
-                        stk[sp++] = k0;
-                    } else {
-                        stk[sp++] = k0;
-                        stk[sp++] = k1;
-                    }
-                } else if (need0) {
-                    stk[sp++] = k0;
-                } else if (need1) {
-                    stk[sp++] = k1;
-                }
-                continue;
-            }
-            if ((j >> 2) == bucket) continue;  // the bucket's own leaves are in the heap
-            const NodeBox bx = a.boxes[j];
-            if (!__any(box_d2<PERIODIC>(ux, uy, uz, bx, a.gmask) <= tau)) continue;
-            n_lv++;
-            const int cnt = (int)bx.count;
-            __syncthreads();
-            if (lane < cnt * 4) {
-                const uint64_t *src = reinterpret_cast<const uint64_t *>(a.recs + j * HOP_LEAF);
-                reinterpret_cast<uint64_t *>(stage)[lane] = src[lane];
-            }
-            __syncthreads();
-            uint32_t pass = 0;
-            for (int k = 0; k < cnt; k++) {
-                const double d2 = PERIODIC ? d2_wrap(qx, qy, qz, stage[k], G) : d2_direct(qx, qy, qz, stage[k]);
-                pass |= (d2 <= tau ? 1u : 0u) << k;
-            }
-            while (__any(pass != 0)) {
-                if (pass != 0) {
-                    const int k = __builtin_ctz(pass);
-                    pass &= pass - 1;
-                    const SortedRec p = stage[k];
-                    const double d2 = PERIODIC ? d2_wrap(qx, qy, qz, p, G) : d2_direct(qx, qy, qz, p);
-                    const uint64_t key = make_key(d2, (uint32_t)p.tk, a);
-                    if (key < tau_key) {
-                        heap_sift(heap, lane, hs, 0, key);
-                        tau_key = heap[lane];
-                        tau = key_d2(tau_key, a.shift);
-                    }
-                }
+                const uint64_t m = __ballot(keep);
+                const int pos = lcnt + (int)__popcll(m & lt_mask);
+                if (keep) leaves[pos] = e;
+                lcnt += (int)__popcll(m);
             }
         }
     }
+    __syncthreads();
+    // unpark the heap
+#pragma unroll
+    for (int s = 5; s < kHeapMax; s++)
+        if (s < hs) heap[s * 64 + lane] = park[s - 5];
+    for (int s = hs; s < kHeapSlots; s++) heap[s * 64 + lane] = 0;
+    __syncthreads();
+    int nleaf_total = 0;
+    for (int i = lane; i < lcnt; i += 64) {
+        const uint32_t e = leaves[i];
+        const int lvl = (int)(e >> 27);
+        const int64_t first = (int64_t)(e & ((1u << 27) - 1)) << lvl;
+        nleaf_total += (int)min((int64_t)1 << lvl, n_leaf_total - first);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) nleaf_total += __shfl_xor(nleaf_total, d);
+
+    // 3. stream the listed leaves, 4 leaves (64 particles) per batch,
+    //    loading batch b+1 while batch b is tested.  When every relevant
+    //    separation stays under half the box, the loading lane moves each
+    //    particle to its image nearest the bucket centre, so the testing
+    //    lanes need no per-pair wrap.
+    bool fastB = true;
+    double cx = 0, cy = 0, cz = 0;
+    if (PERIODIC) {
+        const double r = __builtin_sqrt(tmax);
+        const double half = 0.5 * G;
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+            if ((double)(bb.hi[k] - bb.lo[k]) + 2.0 * r + 2.0 >= half) fastB = false;
+        cx = 0.5 * ((double)bb.lo[0] + (double)bb.hi[0]);
+        cy = 0.5 * ((double)bb.lo[1] + (double)bb.hi[1]);
+        cz = 0.5 * ((double)bb.lo[2] + (double)bb.hi[2]);
+    }
+    const int nbatch = (nleaf_total + 3) >> 2;
+    auto range_len = [&](int r, int64_t *first) -> int {
+        const uint32_t e = leaves[r];
+        const int lvl = (int)(e >> 27);
+        *first = (int64_t)(e & ((1u << 27) - 1)) << lvl;
+        return (int)min((int64_t)1 << lvl, n_leaf_total - *first);
+    };
+    auto cursor_step = [&](int &r, int &o) {
+        int64_t f;
+        if (++o >= range_len(r, &f)) {
+            r++;
+            o = 0;
+        }
+    };
+    int cur_r = 0, cur_o = 0;  // wave-uniform leaf cursor
+    auto fetch = [&](SortedRec &r) -> bool {
+        int rr = cur_r, oo = cur_o;
+        for (int s = 0; s < (lane >> 4); s++) {
+            if (rr >= lcnt) break;
+            cursor_step(rr, oo);
+        }
+        if (rr >= lcnt) return false;
+        int64_t first;
+        range_len(rr, &first);
+        const int64_t leaf = first + oo;
+        if (leaf >= done_lo && leaf < done_hi) return false;  // offered in the seed
+        const int64_t idx = leaf * HOP_LEAF + (lane & 15);
+        if (idx >= a.n) return false;
+        r = a.recs[idx];
+        return true;
+    };
+    SortedRec nxt;
+    bool nxt_ok = nbatch > 0 ? fetch(nxt) : false;
+    for (int bi = 0; bi < nbatch; bi++) {
+        SortedRec r = nxt;
+        const bool ok = nxt_ok;
+        if (ok) {
+            if (PERIODIC && fastB) {
+                const double half = 0.5 * G;
+                const double dx = r.x - cx, dy = r.y - cy, dz = r.z - cz;
+                r.x += dx > half ? -G : (dx < -half ? G : 0.0);
+                r.y += dy > half ? -G : (dy < -half ? G : 0.0);
+                r.z += dz > half ? -G : (dz < -half ? G : 0.0);
+            }
+        } else {
+            r.x = r.y = r.z = 1.0e30;  // never selected
+            r.j = -1;
+            r.tk = -1;
+        }
+        __syncthreads();
+        stage[lane] = r;
+        __syncthreads();
+        for (int s = 0; s < 4 && cur_r < lcnt; s++) cursor_step(cur_r, cur_o);
+        if (bi + 1 < nbatch) nxt_ok = fetch(nxt);
+        if (!__any(ok)) continue;
+        n_lv += 4;
+        uint64_t pass = 0;
+        for (int k0 = 0; k0 < 64; k0 += 16) {
+            SortedRec pr[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) pr[k] = stage[k0 + k];
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const double d2 = (!PERIODIC || fastB) ? d2_direct(qx, qy, qz, pr[k]) : d2_wrap(qx, qy, qz, pr[k], G);
+                pass |= (uint64_t)((d2 <= tau && pr[k].tk != mytk) ? 1u : 0u) << (k0 + k);
+            }
+        }
+        insert_marked(pass, PERIODIC && !fastB);
+    }
+    // write the register levels back so the heap is whole in LDS
+    heap[lane] = H.r0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) heap[(q + 1) * 64 + lane] = H.r1[q];
 
     if (a.counters && lane == 0) {
         atomicAdd(&a.counters[0], n_nodes);
