@@ -120,7 +120,11 @@ const char *hop_last_error(const hop_ctx *ctx);
  * r_max^2 = d^2 to L_i[n_dens-1], h = r_max/2, and
  *   density[i] = sum_t W(|x_i - x_{L_i[t]}|, h) / mean_density
  * with the M4 cubic spline W (unit masses), summed pairwise over a
- * zero-padded 64-slot array.
+ * zero-padded 64-slot array.  The arithmetic is FP64 (round to nearest, no
+ * contraction, correctly rounded division and square root).  Under
+ * HOP_DENSITY_FP32 the same operation sequence runs in FP32 after rounding
+ * 4 d^2 and r_max^2 to FP32; the neighbour lists are unchanged (the search
+ * is exact either way) and the densities are returned widened to FP64.
  *
  * n        particle count
  * pos      [n][3] uint32 coordinates, each < 2^grid_bits (else HOP_ERR_RANGE)

@@ -191,8 +191,6 @@ int hop_density(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
     ctx->err.clear();
     HOPTRY(check_params(ctx, n, p));
     if (!pos || !density) return hop_fail(ctx, HOP_ERR_ARG, "pos and density must be non-NULL");
-    if (p->flags & HOP_DENSITY_FP32)
-        return hop_fail(ctx, HOP_ERR_ARG, "HOP_DENSITY_FP32 is not available in this build");
     HOPTRY(set_device(ctx));
     return hop_density_impl(ctx, n, pos, id, p, density, nbr, (hipStream_t)stream);
 }

@@ -139,6 +139,8 @@ struct KnnArgs {
     uint32_t gmask;
     int front_cap;       // frontier entries the walk may use (<= kFront)
     int vec_store;       // nbr rows 16-byte aligned with k_store % 4 == 0
+    int fp32;            // density arithmetic in FP32 (neighbour search unchanged)
+    float norm32;        // norm rounded to FP32
     int32_t *nbr;
     double *dens;
     const int32_t *tk2j;
@@ -171,6 +173,16 @@ __device__ __forceinline__ double m4_shape(double q2)
     if (q2 < 1.0) return 1.0 - (0.75 * two_q) * q2;
     if (q2 < 4.0) return 0.25 * ((two_q * two_q) * two_q);
     return 0.0;
+}
+
+// The same shape in FP32 (the reduced-precision density variant).
+__device__ __forceinline__ float m4_shape_f32(float q2)
+{
+    float q = __builtin_sqrtf(q2);
+    float two_q = 2.0f - q;
+    if (q2 < 1.0f) return 1.0f - (0.75f * two_q) * q2;
+    if (q2 < 4.0f) return 0.25f * ((two_q * two_q) * two_q);
+    return 0.0f;
 }
 
 template <bool PERIODIC>
@@ -684,34 +696,67 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     if (R == 0) atomicOr(a.dflags, DERR_DEGENERATE);
     if ((double)R >= a.maxd2) atomicOr(a.dflags, DERR_KEYWIDTH);
     const double Rd = (double)(R == 0 ? 1 : R);
-    double part[7];
+    double delta;
+    if (!a.fp32) {
+        double part[7];
 #pragma unroll
-    for (int t = 0; t < 64; t++) {
-        double w;
-        if (t == 0) {
-            w = m4_shape(0.0);
-        } else if (t < a.n_dens) {
-            const uint64_t d2 = v[t - 1] >> a.shift;
-            w = m4_shape((double)(4 * d2) / Rd);
-        } else {
-            w = 0.0;
-        }
-        // pairwise (binary-counter) accumulation: T(a,b) = T(a,m) + T(m,b)
-        double s = w;
-        int lvl = 0;
+        for (int t = 0; t < 64; t++) {
+            double w;
+            if (t == 0) {
+                w = m4_shape(0.0);
+            } else if (t < a.n_dens) {
+                const uint64_t d2 = v[t - 1] >> a.shift;
+                w = m4_shape((double)(4 * d2) / Rd);
+            } else {
+                w = 0.0;
+            }
+            // pairwise (binary-counter) accumulation: T(a,b) = T(a,m) + T(m,b)
+            double s = w;
+            int lvl = 0;
 #pragma unroll
-        for (int b = 0; b < 6; b++) {
-            if (((t >> b) & 1) == 0) break;
-            s = part[b] + s;
-            lvl = b + 1;
+            for (int b = 0; b < 6; b++) {
+                if (((t >> b) & 1) == 0) break;
+                s = part[b] + s;
+                lvl = b + 1;
+            }
+            part[lvl] = s;
         }
-        part[lvl] = s;
+        const double wsum = part[6];
+        const double h2 = Rd * 0.25;
+        const double hh = __builtin_sqrt(h2);
+        const double h3 = h2 * hh;
+        delta = (wsum * a.norm) / h3;
+    } else {
+        // same operation sequence in FP32; 4 d^2 and r_max^2 are rounded to
+        // FP32 on conversion, everything after runs in FP32
+        const float Rf = (float)Rd;
+        float part[7];
+#pragma unroll
+        for (int t = 0; t < 64; t++) {
+            float w;
+            if (t == 0) {
+                w = m4_shape_f32(0.0f);
+            } else if (t < a.n_dens) {
+                const uint64_t d2 = v[t - 1] >> a.shift;
+                w = m4_shape_f32((float)(4 * d2) / Rf);
+            } else {
+                w = 0.0f;
+            }
+            float s = w;
+            int lvl = 0;
+#pragma unroll
+            for (int b = 0; b < 6; b++) {
+                if (((t >> b) & 1) == 0) break;
+                s = part[b] + s;
+                lvl = b + 1;
+            }
+            part[lvl] = s;
+        }
+        const float h2 = Rf * 0.25f;
+        const float hh = __builtin_sqrtf(h2);
+        const float h3 = h2 * hh;
+        delta = (double)((part[6] * a.norm32) / h3);
     }
-    const double wsum = part[6];
-    const double h2 = Rd * 0.25;
-    const double hh = __builtin_sqrt(h2);
-    const double h3 = h2 * hh;
-    const double delta = (wsum * a.norm) / h3;
 
     const int32_t jq = me.j;
     a.dens[jq] = delta;
@@ -830,6 +875,8 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     const double md = p->mean_density > 0 ? p->mean_density
                                           : (double)n / (double)(1ull << (3 * p->grid_bits));
     a.norm = 1.0 / (3.141592653589793 * md);
+    a.fp32 = (p->flags & HOP_DENSITY_FP32) ? 1 : 0;
+    a.norm32 = (float)a.norm;
     a.gsize = (double)glim;
     a.gmask = glim - 1;
     a.front_cap = std::min(std::max(ctx->front_cap, 1), kFront);

@@ -144,11 +144,36 @@ def test_determinism_two_runs(ctx):
         assert np.array_equal(a[k], b[k]), k
 
 
-def test_config2_full_pipeline(ctx, orc):
+@pytest.fixture(scope="module")
+def cfg2(orc):
     p = synth.config(2)
-    r = orc.run(p.pos, mean_density=p.mean_density)
+    return p, orc.run(p.pos, mean_density=p.mean_density)
+
+
+def test_config2_full_pipeline(ctx, cfg2):
+    p, r = cfg2
     g = gpu_run(ctx, p, _params(p))
     assert_parity(g, r, "config2")
+
+
+# FP32 density: r_max^2 and 4 d^2 round once to FP32 (2^-24 relative), the
+# division, square roots, 64-term pairwise sum, h^3 and the final product and
+# quotient add a few ulps each; the largest error seen on 2M particles is
+# below 5e-7 = 8.4 ulp(FP32), so 1e-6 leaves a factor of two.
+FP32_REL_TOL = 1e-6
+
+
+def test_fp32_density_variant(ctx, cfg2):
+    from paper_1001_3411_amd.report import group_change_fraction, max_rel_error
+    p, r = cfg2
+    g = gpu_run(ctx, p, _params(p, density_fp32=True))
+    assert np.array_equal(g["nbr"], r.nbr), "the neighbour search must not change"
+    err = max_rel_error(r.density, g["density"])
+    chg = group_change_fraction(r.group, g["group"])
+    print(f"[fp32] max rel err {err:.3e}, group change fraction {chg:.3e}, "
+          f"groups {g['n_groups']} vs {r.n_groups}", flush=True)
+    assert 0.0 < err <= FP32_REL_TOL
+    assert chg < 1e-3
 
 
 def test_range_error_reported(ctx):
