@@ -57,8 +57,9 @@ struct hop_ctx {
     std::string err;
     int profiling = 0;
     // frontier capacity of the kNN walk; lowering it (environment variable
-    // HOP_FRONT_CAP, read at context creation) routes buckets to the exact
-    // depth-first fallback, which the tests use to cover that path
+    // HOP_FRONT_CAP, read at context creation) stops the walk higher in the
+    // tree, so the streamed list holds whole subtrees; the tests use it to
+    // cover that path
     int front_cap = 1 << 30;
     hop_stats stats{};
 

@@ -11,14 +11,23 @@
 //
 // Search.  One wavefront owns a bucket of 64 consecutive sorted particles,
 // one query per lane.  Each lane keeps its n_dens-1 nearest others in a
-// max-heap in LDS, keyed by (d^2 << B) | tie_key, which orders candidates by
-// (d^2, id) exactly (d^2 is an exact integer held in FP64).  The heap starts
-// from the bucket's own particles, then the wave walks the tree nearest
-// child first; a node is visited when ANY lane's heap could still take a
-// particle from it, a leaf's 16 particles are staged in LDS and tested
-// against every lane's current bound, and candidates that pass are inserted
-// lane by lane.  The walk is wave-uniform, so lanes never diverge on the
-// tree, only on heap insertions.
+// 4-ary max-heap keyed by (d^2 << B) | tie_key, which orders candidates by
+// (d^2, id) exactly (d^2 is an exact integer held in FP64); the heap's top
+// two levels sit in registers, the rest in LDS.  The search runs in three
+// passes:
+//   1. seed: the bucket's own particles and two Morton-neighbour buckets on
+//      each side are offered, which gives every lane a finite bound;
+//   2. walk: a breadth-first descent of the tree, 64 child boxes tested per
+//      step against the boxes and bounds of 8 groups of 8 lanes; it stops at
+//      the level where the surviving frontier would exceed the leaf list,
+//      so the list may hold whole subtrees (ranges of leaves) as well as
+//      single leaves;
+//   3. stream: the listed leaves -- first those touching the bucket's own
+//      box -- are loaded 64 particles at a time, each particle tested by all
+//      lanes against their current bounds, and the ones that pass inserted
+//      lane by lane.
+// Only pruning depends on the bounds; every particle that could belong to
+// a lane's list is offered to it, so the result is the exact kNN.
 //
 // Density.  After the walk the heap is sorted in registers by a bitonic
 // network; the spline weights are summed pairwise (a fixed tree over 64

@@ -197,9 +197,9 @@ def test_degenerate_reported(ctx):
     assert e.value.code == -3
 
 
-def test_depth_first_fallback_parity(orc, monkeypatch):
-    """A tiny frontier capacity sends every bucket to the exact depth-first
-    fallback walk; results must not change."""
+def test_coarse_leaf_ranges_parity(orc, monkeypatch):
+    """A tiny frontier capacity stops the breadth-first walk near the root,
+    so every bucket streams whole subtrees; results must not change."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -212,6 +212,6 @@ def test_depth_first_fallback_parity(orc, monkeypatch):
             r = orc.run(p.pos, periodic=p.periodic, mean_density=p.mean_density,
                         padded=p.padded, padded_rules=pr)
             g = gpu_run(c, p, _params(p, padded_rules=pr))
-            assert_parity(g, r, f"fallback-{p.name}")
+            assert_parity(g, r, f"coarse-{p.name}")
     finally:
         c.close()
