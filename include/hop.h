@@ -205,6 +205,64 @@ int hop_merge(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density
               const uint8_t *padded, const hop_params *p, int32_t *group, int32_t *n_groups,
               hop_group_info *groups, void *stream);
 
+/*
+ * hop_run_batch -- the whole path (density, links, chains, merge, labels)
+ * for n_sub independent subvolumes in one call, with one persistent kNN
+ * launch over all of them.  The shape is that of the paper's per-task work
+ * (section 3.1): every subvolume is a separate non-periodic (or periodic,
+ * by HOP_PERIODIC) problem with its own frame, its own padding flags and
+ * the caller's mean density; neighbours, boundaries and merges never cross
+ * subvolumes.  The result for each subvolume equals what hop_density,
+ * hop_link, hop_groups and hop_merge give for it alone (ids are not taken:
+ * ties go to the smaller index within the subvolume).
+ *
+ * n_sub         number of subvolumes, 1 <= n_sub <= 65536
+ * offsets       HOST [n_sub+1]: subvolume s holds particles
+ *               [offsets[s], offsets[s+1]) of every per-particle array;
+ *               offsets[0] = 0, each subvolume holds >= n_dens particles,
+ *               offsets[n_sub] < 2^31
+ * pos           [n][3] uint32, each subvolume in its own coordinate frame
+ * padded        [n] uint8 or NULL
+ * mean_density  HOST [n_sub] normalisation per subvolume, or NULL; an entry
+ *               <= 0 selects that subvolume's own count / 2^(3*grid_bits)
+ * density, nbr, hop, root, chain_of, group
+ *               [n] (nbr [n][k_store]) outputs, all required; every index
+ *               and number is local to its subvolume (0-based)
+ * n_chains, n_groups   HOST [n_sub] outputs
+ * groups        device [sum of chains] group tables, or NULL: subvolume s
+ *               owns entries [group_off[s], group_off[s+1]); peaks are local
+ * group_off     HOST [n_sub+1] output, or NULL
+ * Synchronises `stream`.
+ */
+int hop_run_batch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, const uint32_t *pos,
+                  const uint8_t *padded, const double *mean_density, const hop_params *p,
+                  double *density, int32_t *nbr, int32_t *hop, int32_t *root, int32_t *chain_of,
+                  int32_t *group, int32_t *n_chains, int32_t *n_groups, hop_group_info *groups,
+                  int64_t *group_off, void *stream);
+
+/*
+ * Launch settings that change speed, never results.  hop_set_tuning takes
+ * effect from the next call on the context.
+ * front_cap         frontier entries the kNN walk may produce before it
+ *                   stops descending and streams whole subtrees (1..1024,
+ *                   default 1024)
+ * persistent_waves  waves of the batched kNN launch (0 = 4 per compute unit,
+ *                   one per SIMD, the most that fit)
+ * xcd_queues        batched launch: 1 = one work chunk per XCD, idle waves
+ *                   move on to the other chunks (default); 0 = one queue
+ * largest_first     batched launch: 1 = subvolumes in decreasing size
+ *                   (default); 0 = in the given order
+ */
+typedef struct hop_tuning {
+    int32_t front_cap;
+    int32_t persistent_waves;
+    int32_t xcd_queues;
+    int32_t largest_first;
+} hop_tuning;
+
+int hop_set_tuning(hop_ctx *ctx, const hop_tuning *t);
+int hop_get_tuning(const hop_ctx *ctx, hop_tuning *t);
+
 /* Synchronises `stream` and reports any error the device recorded since the
    last synchronising call (see the conventions above). */
 int hop_sync(hop_ctx *ctx, void *stream);

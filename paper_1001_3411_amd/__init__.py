@@ -76,6 +76,11 @@ class HopParams:
                        flags)
 
 
+class _Tuning(C.Structure):
+    _fields_ = [("front_cap", C.c_int32), ("persistent_waves", C.c_int32),
+                ("xcd_queues", C.c_int32), ("largest_first", C.c_int32)]
+
+
 _LIB = None
 
 
@@ -101,6 +106,10 @@ def load():
                              C.POINTER(i32), vp]
     L.hop_merge.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, C.POINTER(_Params), vp,
                             C.POINTER(i32), vp, vp]
+    L.hop_run_batch.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(_Params), vp, vp, vp, vp, vp,
+                                vp, vp, vp, vp, vp, vp]
+    L.hop_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+    L.hop_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     L.hop_sync.argtypes = [vp, vp]
     L.hop_set_profiling.argtypes = [vp, C.c_int]
     L.hop_get_stats.argtypes = [vp, C.POINTER(_Stats)]
@@ -249,6 +258,76 @@ class HopContext:
                          stream=stream)
         out.update(density=dens, nbr=nbr, hop=hop, root=root, chain_of=chain_of, n_chains=nc)
         return out
+
+    def run_batch(self, pos, offsets, params: HopParams | None = None, padded=None,
+                  mean_density=None, stream=None):
+        """The whole path for concatenated independent subvolumes (one call).
+
+        pos: [n][3] coordinates of all subvolumes, subvolume s at rows
+        offsets[s]:offsets[s+1]; padded: [n] flags or None; mean_density:
+        one value per subvolume or None (each subvolume's own count).
+        Returns device tensors with every index and number local to its
+        subvolume, and host lists n_chains, n_groups, group_off.
+        """
+        import numpy as np
+        torch = self._torch
+        p = params or HopParams()
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        n_sub = off.size - 1
+        pos = self._dev(pos, torch.int32).view(torch.int32)
+        n = pos.shape[0]
+        if n_sub < 1 or int(off[-1]) != n:
+            raise HopError(-1, "offsets must end at the particle count")
+        dev = pos.device
+        padded = self._dev(padded, torch.uint8)
+        md = None
+        if mean_density is not None:
+            md = np.ascontiguousarray(np.asarray(mean_density, dtype=np.float64))
+            if md.size != n_sub:
+                raise HopError(-1, "one mean density per subvolume")
+        out = {
+            "density": torch.empty(n, dtype=torch.float64, device=dev),
+            "nbr": torch.empty((n, p.k_store), dtype=torch.int32, device=dev),
+            "hop": torch.empty(n, dtype=torch.int32, device=dev),
+            "root": torch.empty(n, dtype=torch.int32, device=dev),
+            "chain_of": torch.empty(n, dtype=torch.int32, device=dev),
+            "group": torch.empty(n, dtype=torch.int32, device=dev),
+        }
+        table = torch.empty((max(n, 1), 3), dtype=torch.int64, device=dev)
+        nch = np.zeros(n_sub, np.int32)
+        ngr = np.zeros(n_sub, np.int32)
+        goff = np.zeros(n_sub + 1, np.int64)
+        cp = p.c()
+        hp = lambda a: None if a is None else C.c_void_p(a.ctypes.data)
+        self._check(self.lib.hop_run_batch(
+            self.h, n_sub, hp(off), _ptr(pos), _ptr(padded), hp(md), C.byref(cp),
+            _ptr(out["density"]), _ptr(out["nbr"]), _ptr(out["hop"]), _ptr(out["root"]),
+            _ptr(out["chain_of"]), _ptr(out["group"]), hp(nch), hp(ngr), _ptr(table), hp(goff),
+            self._stream(stream)))
+        g = int(goff[-1])
+        t = table[:g]
+        out["g_count"] = t[:, 0].clone()
+        out["g_peak"] = (t[:, 1] & 0xFFFFFFFF).to(torch.int32)
+        out["g_peak_dens"] = t[:, 2].contiguous().view(torch.float64)
+        out.update(n_chains=nch.tolist(), n_groups=ngr.tolist(), group_off=goff.tolist(),
+                   offsets=off.tolist())
+        return out
+
+    def set_tuning(self, **kw):
+        """Change launch settings (front_cap, persistent_waves, xcd_queues,
+        largest_first); results never depend on them."""
+        t = _Tuning()
+        self._check(self.lib.hop_get_tuning(self.h, C.byref(t)))
+        for k, v in kw.items():
+            if k not in dict(_Tuning._fields_):
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        self._check(self.lib.hop_set_tuning(self.h, C.byref(t)))
+
+    def tuning(self) -> dict:
+        t = _Tuning()
+        self._check(self.lib.hop_get_tuning(self.h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in _Tuning._fields_}
 
     def set_profiling(self, on: bool):
         self._check(self.lib.hop_set_profiling(self.h, int(on)))

@@ -73,7 +73,7 @@ int hop_check_device(hop_ctx *ctx, hipStream_t s, const char *stage)
     return hop_fail(ctx, HOP_ERR_HIP, where + "unknown device error");
 }
 
-static int check_params(hop_ctx *ctx, int64_t n, const hop_params *p)
+int hop_check_params(hop_ctx *ctx, int64_t n, const hop_params *p)
 {
     if (!p) return hop_fail(ctx, HOP_ERR_ARG, "params is NULL");
     if (!(1 <= p->n_merge && p->n_merge <= p->n_hop && p->n_hop <= p->k_store &&
@@ -92,7 +92,7 @@ static int check_params(hop_ctx *ctx, int64_t n, const hop_params *p)
     return HOP_OK;
 }
 
-static int set_device(hop_ctx *ctx)
+int hop_set_device(hop_ctx *ctx)
 {
     HOPCHK(ctx, hipSetDevice(ctx->device));
     return HOP_OK;
@@ -127,8 +127,14 @@ int hop_ctx_create(int device, hop_ctx **out)
     hop_ctx *ctx = new (std::nothrow) hop_ctx();
     if (!ctx) return HOP_ERR_NOMEM;
     ctx->device = device;
-    if (const char *fc = std::getenv("HOP_FRONT_CAP")) ctx->front_cap = std::atoi(fc);
-    int rc = set_device(ctx);
+    int rc = hop_set_device(ctx);
+    if (rc == HOP_OK) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
+            ctx->n_cu = cu;
+        else
+            (void)hipGetLastError();
+    }
     if (rc == HOP_OK) rc = hop_reserve(ctx, ctx->flags, 4096);
     if (rc == HOP_OK && hipMemset(ctx->flags.ptr, 0, 4096) != hipSuccess) rc = HOP_ERR_HIP;
     if (rc == HOP_OK && hipHostMalloc((void **)&ctx->hflags, 4096, 0) != hipSuccess) rc = HOP_ERR_NOMEM;
@@ -150,7 +156,7 @@ void hop_ctx_destroy(hop_ctx *ctx)
                       &ctx->recs, &ctx->boxes, &ctx->tk, &ctx->tk2j, &ctx->flags,
                       &ctx->work_a, &ctx->work_b, &ctx->work_c, &ctx->work_d, &ctx->work_e,
                       &ctx->work_f, &ctx->hash_keys, &ctx->hash_vals, &ctx->edges_lo,
-                      &ctx->edges_hi, &ctx->edges_s};
+                      &ctx->edges_hi, &ctx->edges_s, &ctx->batch_tab, &ctx->batch_aux};
     for (DevBuf *b : bufs)
         if (b->ptr) hipFree(b->ptr);
     if (ctx->hflags) hipHostFree(ctx->hflags);
@@ -169,6 +175,27 @@ int hop_set_profiling(hop_ctx *ctx, int on)
     return HOP_OK;
 }
 
+int hop_set_tuning(hop_ctx *ctx, const hop_tuning *t)
+{
+    if (!ctx || !t) return HOP_ERR_ARG;
+    ctx->err.clear();
+    if (t->front_cap < 1 || t->front_cap > 1024)
+        return hop_fail(ctx, HOP_ERR_ARG, "front_cap must be in [1, 1024]");
+    if (t->persistent_waves < 0 || t->persistent_waves > (1 << 20))
+        return hop_fail(ctx, HOP_ERR_ARG, "persistent_waves must be in [0, 2^20]");
+    if ((t->xcd_queues != 0 && t->xcd_queues != 1) || (t->largest_first != 0 && t->largest_first != 1))
+        return hop_fail(ctx, HOP_ERR_ARG, "xcd_queues and largest_first must be 0 or 1");
+    ctx->tuning = *t;
+    return HOP_OK;
+}
+
+int hop_get_tuning(const hop_ctx *ctx, hop_tuning *t)
+{
+    if (!ctx || !t) return HOP_ERR_ARG;
+    *t = ctx->tuning;
+    return HOP_OK;
+}
+
 int hop_get_stats(const hop_ctx *ctx, hop_stats *out)
 {
     if (!ctx || !out) return HOP_ERR_ARG;
@@ -180,7 +207,7 @@ int hop_sync(hop_ctx *ctx, void *stream)
 {
     if (!ctx) return HOP_ERR_ARG;
     ctx->err.clear();
-    HOPTRY(set_device(ctx));
+    HOPTRY(hop_set_device(ctx));
     return hop_check_device(ctx, (hipStream_t)stream, "hop_sync");
 }
 
@@ -189,9 +216,9 @@ int hop_density(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
 {
     if (!ctx) return HOP_ERR_ARG;
     ctx->err.clear();
-    HOPTRY(check_params(ctx, n, p));
+    HOPTRY(hop_check_params(ctx, n, p));
     if (!pos || !density) return hop_fail(ctx, HOP_ERR_ARG, "pos and density must be non-NULL");
-    HOPTRY(set_device(ctx));
+    HOPTRY(hop_set_device(ctx));
     return hop_density_impl(ctx, n, pos, id, p, density, nbr, (hipStream_t)stream);
 }
 
@@ -201,9 +228,9 @@ int hop_link(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
 {
     if (!ctx) return HOP_ERR_ARG;
     ctx->err.clear();
-    HOPTRY(check_params(ctx, n, p));
+    HOPTRY(hop_check_params(ctx, n, p));
     if (!nbr || !density || !hop) return hop_fail(ctx, HOP_ERR_ARG, "nbr, density and hop must be non-NULL");
-    HOPTRY(set_device(ctx));
+    HOPTRY(hop_set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
     const int32_t *tk = nullptr;
     if (id) {
@@ -219,10 +246,10 @@ int hop_groups(hop_ctx *ctx, int64_t n, const int32_t *hop, const double *densit
 {
     if (!ctx) return HOP_ERR_ARG;
     ctx->err.clear();
-    HOPTRY(check_params(ctx, n, p));
+    HOPTRY(hop_check_params(ctx, n, p));
     if (!hop || !density || !root || !chain_of || !n_chains)
         return hop_fail(ctx, HOP_ERR_ARG, "hop, density, root, chain_of and n_chains must be non-NULL");
-    HOPTRY(set_device(ctx));
+    HOPTRY(hop_set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
     const int32_t *tk = nullptr;
     if (id) {
@@ -239,11 +266,11 @@ int hop_merge(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density
 {
     if (!ctx) return HOP_ERR_ARG;
     ctx->err.clear();
-    HOPTRY(check_params(ctx, n, p));
+    HOPTRY(hop_check_params(ctx, n, p));
     if (!nbr || !density || !root || !chain_of || !group || !n_groups)
         return hop_fail(ctx, HOP_ERR_ARG, "nbr, density, root, chain_of, group and n_groups must be non-NULL");
     if (n_chains < 0 || n_chains > n) return hop_fail(ctx, HOP_ERR_ARG, "n_chains outside [0, n]");
-    HOPTRY(set_device(ctx));
+    HOPTRY(hop_set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
     const int32_t *tk = nullptr;
     if (id) {
@@ -251,7 +278,7 @@ int hop_merge(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density
         tk = (const int32_t *)ctx->tk.ptr;
     }
     return hop_merge_impl(ctx, n, nbr, density, root, chain_of, n_chains, tk, padded, p, group,
-                          n_groups, groups, s);
+                          n_groups, groups, nullptr, 0, nullptr, s);
 }
 
 }  // extern "C"

@@ -56,11 +56,8 @@ struct hop_ctx {
     int device = 0;
     std::string err;
     int profiling = 0;
-    // frontier capacity of the kNN walk; lowering it (environment variable
-    // HOP_FRONT_CAP, read at context creation) stops the walk higher in the
-    // tree, so the streamed list holds whole subtrees; the tests use it to
-    // cover that path
-    int front_cap = 1 << 30;
+    int n_cu = 256;  // compute units of the device
+    hop_tuning tuning{1024, 0, 1, 1};
     hop_stats stats{};
 
     // device scratch
@@ -73,6 +70,7 @@ struct hop_ctx {
     DevBuf work_a, work_b, work_c, work_d, work_e, work_f;  // stage scratch
     DevBuf hash_keys, hash_vals;
     DevBuf edges_lo, edges_hi, edges_s;
+    DevBuf batch_tab, batch_aux;  // batched launch: work description, per-subvolume bases
     // pinned host mirror of the device counters
     int64_t *hflags = nullptr;
 
@@ -88,6 +86,8 @@ struct hop_ctx {
 int hop_fail(hop_ctx *ctx, int code, const std::string &msg);
 int hop_hip_fail(hop_ctx *ctx, hipError_t e, const char *what);
 int hop_reserve(hop_ctx *ctx, DevBuf &b, size_t bytes);
+int hop_check_params(hop_ctx *ctx, int64_t n, const hop_params *p);
+int hop_set_device(hop_ctx *ctx);
 // Reads the device error bits (synchronising the stream) and turns them into
 // a return code.
 int hop_check_device(hop_ctx *ctx, hipStream_t s, const char *stage);
@@ -127,13 +127,26 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
 int hop_link_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
                   const int32_t *tk, const uint8_t *padded, const hop_params *p, int32_t *hop,
                   hipStream_t s);
+// Leaves the exclusive scan of the chain-root flags (indexed by tie key)
+// in ctx->work_a: entry k = number of chains whose root has tie key < k.
 int hop_groups_impl(hop_ctx *ctx, int64_t n, const int32_t *hop, const double *density,
                     const int32_t *tk, const hop_params *p, int32_t *root, int32_t *chain_of,
                     int32_t *n_chains, hipStream_t s);
+// chain_base (device, [n_sub+1], or NULL): for a batch, the first chain of
+// each subvolume; the halos are then ordered by subvolume first, and
+// group_first (device, [n_sub]) receives the first group of each
+// subvolume that has one (entries of the others are left alone).
 int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
                    const int32_t *root, const int32_t *chain_of, int32_t n_chains,
                    const int32_t *tk, const uint8_t *padded, const hop_params *p, int32_t *group,
-                   int32_t *n_groups, hop_group_info *groups, hipStream_t s);
+                   int32_t *n_groups, hop_group_info *groups, const int32_t *chain_base,
+                   int32_t n_sub, int32_t *group_first, hipStream_t s);
+// kNN + density for a batch of subvolumes (offsets on the host); neighbour
+// lists hold batch-wide input indices.  *sub_off_dev receives a device copy
+// of the offsets, valid until the next batched call.
+int hop_density_batch_impl(hop_ctx *ctx, int32_t n_sub, const int64_t *off, const uint32_t *pos,
+                           const double *mean_density, const hop_params *p, double *density,
+                           int32_t *nbr, int64_t **sub_off_dev, hipStream_t s);
 
 static inline int64_t hop_div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static inline int hop_grid(int64_t items, int per_block)

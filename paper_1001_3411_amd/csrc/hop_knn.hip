@@ -36,6 +36,8 @@
 #include "hop_internal.h"
 
 #include <algorithm>
+#include <cstring>
+#include <vector>
 
 namespace {
 
@@ -155,6 +157,20 @@ struct KnnArgs {
     const int32_t *tk2j;
     uint32_t *dflags;
     unsigned long long *counters;  // [0] nodes tested, [1] leaves scanned (NULL = off)
+};
+
+// Work description of a batched launch (device arrays, see k_knn_batch).
+struct BatchArgs {
+    const int64_t *sub_off;   // [n_sub + 1] particle ranges (sorted = input ranges)
+    const int32_t *order;     // [n_sub] processing order of the subvolumes
+    const int64_t *item_off;  // [n_sub + 1] first bucket of order[k]
+    const double *norm;       // [n_sub] 1 / (pi * mean density)
+    const float *norm32;      // [n_sub] the same rounded to FP32
+    uint32_t *queue;          // [8] chunk cursors, zero at launch
+    uint32_t *done;           // [n_sub] buckets finished, zero at launch
+    int64_t n_items;
+    int n_sub;
+    int xcd_queues;           // 1: one chunk per XCD; 0: one shared queue
 };
 
 // (d^2 << shift) | tk.  d^2 is an exact integer below 2^52 held in a double:
@@ -351,26 +367,23 @@ __device__ __forceinline__ void rh_replace_root(RegHeap &H, uint64_t *heap, int 
     if (deeper >= 0) lds_sift(heap, lane, hs, deeper, x);
 }
 
+// One bucket: the bcount (<= 64) sorted particles from b0, all inside the
+// particle range [plo, phi) of one independent problem (the whole box, or
+// one subvolume of a batch).  Candidates outside [plo, phi) are never
+// offered, and the walk never enters a subtree whose leaves lie outside it.
+// heap, stage and leaves are the wave's LDS buffers.
 template <bool PERIODIC, bool IDS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_density(KnnArgs a)
+__device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, const int bcount,
+                                           const int64_t plo, const int64_t phi,
+                                           const double norm, const float norm32, uint64_t *heap,
+                                           SortedRec *stage, uint32_t *leaves)
 {
-    __shared__ uint64_t heap[kHeapSlots * 64];
-    __shared__ SortedRec stage[64];
-    __shared__ uint32_t leaves[kLeafList];
     // the walk's two frontier buffers live in the heap area until the heap
     // is filled
     uint32_t *front_a = reinterpret_cast<uint32_t *>(heap);
     uint32_t *front_b = front_a + kFrontLevel;
 
     const int lane = threadIdx.x;
-    // XCD-aware bucket order: consecutive blocks land on different XCDs, so
-    // give each XCD a contiguous run of buckets (neighbouring buckets share
-    // candidate leaves in that XCD's L2).
-    const int64_t bid = blockIdx.x;
-    const int64_t bucket = (bid & 7) * a.xcd_chunk + (bid >> 3);
-    if (bucket >= a.n_buckets) return;
-    const int64_t b0 = bucket * HOP_BUCKET;
-    const int bcount = (int)min((int64_t)HOP_BUCKET, a.n - b0);
     const bool active = lane < bcount;
     const int hs = a.hs;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -429,9 +442,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     // ... and offer the rest of the bucket (hs < 63 only) and two
     //    Morton-neighbour buckets on each side (exact minimum image)
     for (int side = 0; side < 5; side++) {
-        const int64_t nb0 = b0 + (side - 2) * HOP_BUCKET;
-        if (nb0 < 0 || nb0 >= a.n) continue;
-        const int ncnt = (int)min((int64_t)HOP_BUCKET, a.n - nb0);
+        const int64_t nb0 = max(b0 + (side - 2) * HOP_BUCKET, plo);
+        const int64_t nb1 = side == 2 ? b0 + bcount : min(b0 + (side - 1) * HOP_BUCKET, phi);
+        if (nb0 >= nb1) continue;
+        const int ncnt = (int)(nb1 - nb0);
         if (side == 2 && hs >= HOP_BUCKET - 1) continue;
         __syncthreads();
         if (lane < ncnt) stage[lane] = a.recs[nb0 + lane];
@@ -452,9 +466,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         }
         insert_marked(pass, PERIODIC);
     }
-    // leaves whose particles have all been offered
-    const int64_t done_lo = max((int64_t)0, 4 * (bucket - 2));
-    const int64_t done_hi = min(n_leaf_total, 4 * (bucket + 3));
+    // particles already offered by the seed, and the leaves of [plo, phi)
+    const int64_t seed_lo = max(b0 - 2 * HOP_BUCKET, plo);
+    const int64_t seed_hi = min(b0 + 3 * HOP_BUCKET, phi);
+    const int64_t leaf_lo = plo / HOP_LEAF, leaf_hi = (phi - 1) / HOP_LEAF;
 
     double tmax = tau;
 #pragma unroll
@@ -495,7 +510,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     //    group's box; 64 lanes test 64 children at once.  The frontier uses
     //    the heap's LDS levels, so levels 2-3 of the heap are parked in the
     //    leaf list meanwhile.
-    const NodeBox bb = a.boxes[a.lv.off[2] + bucket];
+    NodeBox bb;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        bb.lo[k] = gbox[0].lo[k];
+        bb.hi[k] = gbox[0].hi[k];
+#pragma unroll
+        for (int g = 1; g < 8; g++) {
+            bb.lo[k] = min(bb.lo[k], gbox[g].lo[k]);
+            bb.hi[k] = max(bb.hi[k], gbox[g].hi[k]);
+        }
+    }
     // park heap levels 2..3 (slots 5..hs-1) in registers
     uint64_t park[kHeapMax - 5];
 #pragma unroll
@@ -514,7 +539,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
             uint32_t child = 0;
             if (ni < fcnt) {
                 child = 2 * fc[ni] + (uint32_t)(lane & 1);
-                if (child < (uint32_t)a.lv.cnt[h - 1]) {
+                const int64_t cfirst = (int64_t)child << (h - 1);
+                const int64_t clast = cfirst + ((int64_t)1 << (h - 1)) - 1;
+                if (child < (uint32_t)a.lv.cnt[h - 1] && cfirst <= leaf_hi && clast >= leaf_lo) {
                     const NodeBox cb = a.boxes[a.lv.off[h - 1] + child];
 #pragma unroll
                     for (int g = 0; g < 8; g++) need |= boxbox_d2<PERIODIC>(gbox[g], cb, a.gmask) <= gt[g];
@@ -548,7 +575,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
                     e = node | ((uint32_t)hf << 27);
                     const int64_t first = (int64_t)node << hf;
                     const int64_t last = min(first + ((int64_t)1 << hf), n_leaf_total);
-                    const bool done = hf == 0 && first >= done_lo && last <= done_hi;
+                    const bool done = hf == 0 && first * HOP_LEAF >= seed_lo &&
+                                      min(last * HOP_LEAF, a.n) <= seed_hi;
                     const NodeBox nb = a.boxes[a.lv.off[hf] + node];
                     const bool near = boxbox_d2<PERIODIC>(bb, nb, a.gmask) == 0.0;
                     keep = !done && (pass == 0 ? near : !near);
@@ -618,10 +646,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         if (rr >= lcnt) return false;
         int64_t first;
         range_len(rr, &first);
-        const int64_t leaf = first + oo;
-        if (leaf >= done_lo && leaf < done_hi) return false;  // offered in the seed
-        const int64_t idx = leaf * HOP_LEAF + (lane & 15);
-        if (idx >= a.n) return false;
+        const int64_t idx = (first + oo) * HOP_LEAF + (lane & 15);
+        if (idx < plo || idx >= phi) return false;          // another problem
+        if (idx >= seed_lo && idx < seed_hi) return false;  // offered in the seed
         r = a.recs[idx];
         return true;
     };
@@ -734,7 +761,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         const double h2 = Rd * 0.25;
         const double hh = __builtin_sqrt(h2);
         const double h3 = h2 * hh;
-        delta = (wsum * a.norm) / h3;
+        delta = (wsum * norm) / h3;
     } else {
         // same operation sequence in FP32; 4 d^2 and r_max^2 are rounded to
         // FP32 on conversion, everything after runs in FP32
@@ -764,7 +791,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         const float h2 = Rf * 0.25f;
         const float hh = __builtin_sqrtf(h2);
         const float h3 = h2 * hh;
-        delta = (double)((part[6] * a.norm32) / h3);
+        delta = (double)((part[6] * norm32) / h3);
     }
 
     const int32_t jq = me.j;
@@ -794,11 +821,225 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     }
 }
 
+// One box: one wave per bucket of 64 sorted particles.  Consecutive blocks
+// land on different XCDs, so each XCD gets a contiguous run of buckets
+// (neighbouring buckets share candidate leaves in that XCD's L2).
+template <bool PERIODIC, bool IDS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_density(KnnArgs a)
+{
+    __shared__ uint64_t heap[kHeapSlots * 64];
+    __shared__ SortedRec stage[64];
+    __shared__ uint32_t leaves[kLeafList];
+    const int64_t bid = blockIdx.x;
+    const int64_t bucket = (bid & 7) * a.xcd_chunk + (bid >> 3);
+    if (bucket >= a.n_buckets) return;
+    const int64_t b0 = bucket * HOP_BUCKET;
+    knn_bucket<PERIODIC, IDS>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n, a.norm,
+                              a.norm32, heap, stage, leaves);
+}
+
+// A batch of independent subvolumes, one persistent wave per SIMD.  Work
+// items are buckets, numbered subvolume by subvolume in the order `order`
+// (largest first by default) and cut into one contiguous chunk per XCD;
+// a wave takes items from its XCD's chunk and, when that runs dry, from the
+// next chunks in turn, and exits when all are dry.
+template <bool PERIODIC>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_batch(KnnArgs a,
+                                                                                             BatchArgs b)
+{
+    __shared__ uint64_t heap[kHeapSlots * 64];
+    __shared__ SortedRec stage[64];
+    __shared__ uint32_t leaves[kLeafList];
+    const int lane = threadIdx.x;
+    const int nq = b.xcd_queues ? 8 : 1;
+    const int64_t chunk = (b.n_items + nq - 1) / nq;
+    int q = b.xcd_queues ? (int)(blockIdx.x & 7) : 0;
+    int dry = 0;
+    while (dry < nq) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(&b.queue[q], 1u);
+        t = (uint32_t)__shfl((int)t, 0);
+        const int64_t item = (int64_t)q * chunk + (int64_t)t;
+        if ((int64_t)t >= chunk || item >= b.n_items) {
+            q = q + 1 == nq ? 0 : q + 1;
+            dry++;
+            continue;
+        }
+        // k: item_off[k] <= item < item_off[k + 1]
+        int lo = 0, hi = b.n_sub;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (b.item_off[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const int sv = b.order[lo];
+        const int64_t plo = b.sub_off[sv], phi = b.sub_off[sv + 1];
+        const int64_t b0 = plo + (item - b.item_off[lo]) * HOP_BUCKET;
+        __syncthreads();
+        knn_bucket<PERIODIC, false>(a, b0, (int)min((int64_t)HOP_BUCKET, phi - b0), plo, phi,
+                                    b.norm[sv], b.norm32[sv], heap, stage, leaves);
+        if (lane == 0) atomicAdd(&b.done[sv], 1u);
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+
+namespace {
+
+// Morton keys of a batch: the subvolume number in the top sub_bits bits,
+// then the Morton code without its lowest sub_bits - 1 bits.  The order
+// inside a subvolume only affects locality, never a result.
+__global__ void k_morton_batch(const uint32_t *__restrict__ pos, int64_t n, uint32_t glim,
+                               const int64_t *__restrict__ sub_off, int n_sub, int sub_bits,
+                               uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                               uint32_t *__restrict__ dflags)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = n_sub;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sub_off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    uint32_t x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    if (x >= glim || y >= glim || z >= glim) {
+        atomicOr(dflags, DERR_RANGE);
+        x = min(x, glim - 1);
+        y = min(y, glim - 1);
+        z = min(z, glim - 1);
+    }
+    const uint64_t m = (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+    keys[i] = ((uint64_t)lo << (64 - sub_bits)) | (m >> (sub_bits - 1));
+    vals[i] = (uint32_t)i;
+}
+
+// HIP events that are destroyed on every exit path
+struct Events {
+    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    ~Events()
+    {
+        for (auto &x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    hipError_t create()
+    {
+        for (auto &x : e) {
+            hipError_t r = hipEventCreate(&x);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+};
+
+// Sorted copy (permutation in ctx->vals_a) and the implicit tree over it.
+int build_tree(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int32_t *tk, uint32_t glim,
+               hipStream_t s, TreeLevels &lv, SortedRec *&recs, NodeBox *&boxes)
+{
+    const uint32_t *perm = (const uint32_t *)ctx->vals_a.ptr;
+    HOPTRY(hop_reserve(ctx, ctx->recs, (size_t)n * sizeof(SortedRec)));
+    recs = (SortedRec *)ctx->recs.ptr;
+    k_gather_recs<<<hop_grid(n, 256), 256, 0, s>>>(pos, perm, tk, n, glim, recs);
+    HOPCHK(ctx, hipGetLastError());
+
+    lv = TreeLevels{};
+    const int64_t n_leaves = hop_div_up(n, HOP_LEAF);
+    int64_t total = 0, cnt = n_leaves;
+    int lvl = 0;
+    for (;;) {
+        if (lvl >= HOP_MAX_LEVELS) return hop_fail(ctx, HOP_ERR_ARG, "tree too deep");
+        lv.off[lvl] = total;
+        lv.cnt[lvl] = (int32_t)cnt;
+        total += cnt;
+        if (cnt == 1 && lvl >= 2) break;
+        cnt = hop_div_up(cnt, 2);
+        lvl++;
+    }
+    lv.top = lvl;
+    HOPTRY(hop_reserve(ctx, ctx->boxes, (size_t)total * sizeof(NodeBox)));
+    boxes = (NodeBox *)ctx->boxes.ptr;
+    k_leaf_boxes<<<hop_grid(n_leaves, 256), 256, 0, s>>>(recs, n, n_leaves, boxes);
+    HOPCHK(ctx, hipGetLastError());
+    for (int h = 1; h <= lv.top; h++) {
+        k_level_boxes<<<hop_grid(lv.cnt[h], 256), 256, 0, s>>>(boxes, lv.off[h - 1], lv.cnt[h - 1],
+                                                               lv.off[h], lv.cnt[h]);
+        HOPCHK(ctx, hipGetLastError());
+    }
+    return HOP_OK;
+}
+
+double norm_of(const hop_params *p, double mean_density, int64_t n)
+{
+    const double md = mean_density > 0 ? mean_density
+                                        : (double)n / (double)(1ull << (3 * p->grid_bits));
+    return 1.0 / (3.141592653589793 * md);
+}
+
+// Fields shared by the single-box and batched launches.
+void base_args(hop_ctx *ctx, KnnArgs &a, int64_t n, const hop_params *p, SortedRec *recs,
+               NodeBox *boxes, const TreeLevels &lv, double *density, int32_t *nbr,
+               const int32_t *tk2j)
+{
+    const uint32_t glim = 1u << p->grid_bits;
+    a = KnnArgs{};
+    a.recs = recs;
+    a.boxes = boxes;
+    a.lv = lv;
+    a.n = n;
+    a.n_buckets = hop_div_up(n, HOP_BUCKET);
+    a.xcd_chunk = hop_div_up(a.n_buckets, 8);
+    a.hs = p->n_dens - 1;
+    a.n_dens = p->n_dens;
+    a.k_store = p->k_store;
+    int shift = 1;
+    while (shift < 31 && ((int64_t)1 << shift) < n) shift++;
+    a.shift = shift;
+    a.tk_mask = (1ull << shift) - 1;
+    a.maxd2 = (double)((~0ull) >> shift);
+    if (a.maxd2 > 9.0e15) a.maxd2 = 9.0e15;  // d^2 < 3*2^42 never reaches this
+    a.fp32 = (p->flags & HOP_DENSITY_FP32) ? 1 : 0;
+    a.gsize = (double)glim;
+    a.gmask = glim - 1;
+    a.front_cap = std::min(std::max((int)ctx->tuning.front_cap, 1), kFront);
+    a.vec_store = nbr && (p->k_store % 4 == 0) && (((uintptr_t)nbr & 15) == 0);
+    a.nbr = nbr;
+    a.dens = density;
+    a.tk2j = tk2j;
+    a.dflags = (uint32_t *)ctx->flags.ptr;
+    a.counters = nullptr;
+}
+
+int finish_stats(hop_ctx *ctx, Events &ev, const KnnArgs &a, int64_t n)
+{
+    if (!ctx->profiling) return HOP_OK;
+    HOPCHK(ctx, hipEventSynchronize(ev.e[2]));
+    float t0 = 0, t1 = 0;
+    HOPCHK(ctx, hipEventElapsedTime(&t0, ev.e[0], ev.e[1]));
+    HOPCHK(ctx, hipEventElapsedTime(&t1, ev.e[1], ev.e[2]));
+    unsigned long long c[2] = {0, 0};
+    if (a.counters) HOPCHK(ctx, hipMemcpy(c, a.counters, 16, hipMemcpyDeviceToHost));
+    ctx->stats.ms_sort = t0;
+    ctx->stats.ms_knn = t1;
+    ctx->stats.n = n;
+    ctx->stats.nodes_visited = (int64_t)c[0];
+    ctx->stats.leaves_scanned = (int64_t)c[1];
+    return HOP_OK;
+}
+
+int start_counters(hop_ctx *ctx, KnnArgs &a, hipStream_t s)
+{
+    if (ctx->profiling & 2) {
+        a.counters = (unsigned long long *)((char *)ctx->flags.ptr + 256);
+        HOPCHK(ctx, hipMemsetAsync(a.counters, 0, 16, s));
+    }
+    return HOP_OK;
+}
+
+}  // namespace
 
 int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
                      const hop_params *p, double *density, int32_t *nbr, hipStream_t s)
@@ -807,10 +1048,10 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     const bool periodic = (p->flags & HOP_PERIODIC) != 0;
     uint32_t *dflags = (uint32_t *)ctx->flags.ptr;
 
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    Events ev;
     if (ctx->profiling) {
-        for (auto &e : ev) HOPCHK(ctx, hipEventCreate(&e));
-        HOPCHK(ctx, hipEventRecord(ev[0], s));
+        HOPCHK(ctx, ev.create());
+        HOPCHK(ctx, hipEventRecord(ev.e[0], s));
     }
 
     const int32_t *tk = nullptr, *tk2j = nullptr;
@@ -834,72 +1075,18 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     ctx->perm_n = n;
 
     // 2. sorted copy and tree
-    HOPTRY(hop_reserve(ctx, ctx->recs, (size_t)n * sizeof(SortedRec)));
-    SortedRec *recs = (SortedRec *)ctx->recs.ptr;
-    k_gather_recs<<<hop_grid(n, 256), 256, 0, s>>>(pos, perm, tk, n, glim, recs);
-    HOPCHK(ctx, hipGetLastError());
-
-    TreeLevels lv{};
-    int64_t n_leaves = hop_div_up(n, HOP_LEAF);
-    int64_t total = 0, cnt = n_leaves;
-    int lvl = 0;
-    for (;;) {
-        if (lvl >= HOP_MAX_LEVELS) return hop_fail(ctx, HOP_ERR_ARG, "tree too deep");
-        lv.off[lvl] = total;
-        lv.cnt[lvl] = (int32_t)cnt;
-        total += cnt;
-        if (cnt == 1 && lvl >= 2) break;
-        cnt = hop_div_up(cnt, 2);
-        lvl++;
-    }
-    lv.top = lvl;
-    HOPTRY(hop_reserve(ctx, ctx->boxes, (size_t)total * sizeof(NodeBox)));
-    NodeBox *boxes = (NodeBox *)ctx->boxes.ptr;
-    k_leaf_boxes<<<hop_grid(n_leaves, 256), 256, 0, s>>>(recs, n, n_leaves, boxes);
-    HOPCHK(ctx, hipGetLastError());
-    for (int h = 1; h <= lv.top; h++) {
-        k_level_boxes<<<hop_grid(lv.cnt[h], 256), 256, 0, s>>>(boxes, lv.off[h - 1], lv.cnt[h - 1],
-                                                               lv.off[h], lv.cnt[h]);
-        HOPCHK(ctx, hipGetLastError());
-    }
-    if (ctx->profiling) HOPCHK(ctx, hipEventRecord(ev[1], s));
+    TreeLevels lv;
+    SortedRec *recs = nullptr;
+    NodeBox *boxes = nullptr;
+    HOPTRY(build_tree(ctx, n, pos, tk, glim, s, lv, recs, boxes));
+    if (ctx->profiling) HOPCHK(ctx, hipEventRecord(ev.e[1], s));
 
     // 3. kNN + density
-    KnnArgs a{};
-    a.recs = recs;
-    a.boxes = boxes;
-    a.lv = lv;
-    a.n = n;
-    a.n_buckets = hop_div_up(n, HOP_BUCKET);
-    a.xcd_chunk = hop_div_up(a.n_buckets, 8);
-    a.hs = p->n_dens - 1;
-    a.n_dens = p->n_dens;
-    a.k_store = p->k_store;
-    int shift = 1;
-    while (shift < 31 && ((int64_t)1 << shift) < n) shift++;
-    a.shift = shift;
-    a.tk_mask = (1ull << shift) - 1;
-    a.maxd2 = (double)((~0ull) >> shift);
-    if (a.maxd2 > 9.0e15) a.maxd2 = 9.0e15;  // d^2 < 3*2^42 never reaches this
-    const double md = p->mean_density > 0 ? p->mean_density
-                                          : (double)n / (double)(1ull << (3 * p->grid_bits));
-    a.norm = 1.0 / (3.141592653589793 * md);
-    a.fp32 = (p->flags & HOP_DENSITY_FP32) ? 1 : 0;
+    KnnArgs a;
+    base_args(ctx, a, n, p, recs, boxes, lv, density, nbr, tk2j);
+    a.norm = norm_of(p, p->mean_density, n);
     a.norm32 = (float)a.norm;
-    a.gsize = (double)glim;
-    a.gmask = glim - 1;
-    a.front_cap = std::min(std::max(ctx->front_cap, 1), kFront);
-    a.vec_store = nbr && (p->k_store % 4 == 0) && (((uintptr_t)nbr & 15) == 0);
-    a.nbr = nbr;
-    a.dens = density;
-    a.tk2j = tk2j;
-    a.dflags = dflags;
-    a.counters = nullptr;
-    unsigned long long *counters = (unsigned long long *)((char *)ctx->flags.ptr + 256);
-    if (ctx->profiling & 2) {
-        a.counters = counters;
-        HOPCHK(ctx, hipMemsetAsync(a.counters, 0, 16, s));
-    }
+    HOPTRY(start_counters(ctx, a, s));
     const int64_t grid = a.xcd_chunk * 8;
     if (grid >= ((int64_t)1 << 31)) return hop_fail(ctx, HOP_ERR_ARG, "too many particles");
     if (periodic) {
@@ -910,21 +1097,110 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
         else k_knn_density<false, false><<<(int)grid, 64, 0, s>>>(a);
     }
     HOPCHK(ctx, hipGetLastError());
+    if (ctx->profiling) HOPCHK(ctx, hipEventRecord(ev.e[2], s));
+    return finish_stats(ctx, ev, a, n);
+}
 
+int hop_density_batch_impl(hop_ctx *ctx, int32_t n_sub, const int64_t *off, const uint32_t *pos,
+                           const double *mean_density, const hop_params *p, double *density,
+                           int32_t *nbr, int64_t **sub_off_dev, hipStream_t s)
+{
+    const uint32_t glim = 1u << p->grid_bits;
+    const bool periodic = (p->flags & HOP_PERIODIC) != 0;
+    uint32_t *dflags = (uint32_t *)ctx->flags.ptr;
+    const int64_t n = off[n_sub];
+    ctx->perm_n = 0;
+
+    Events ev;
     if (ctx->profiling) {
-        HOPCHK(ctx, hipEventRecord(ev[2], s));
-        HOPCHK(ctx, hipEventSynchronize(ev[2]));
-        float t0 = 0, t1 = 0;
-        HOPCHK(ctx, hipEventElapsedTime(&t0, ev[0], ev[1]));
-        HOPCHK(ctx, hipEventElapsedTime(&t1, ev[1], ev[2]));
-        unsigned long long c[2] = {0, 0};
-        if (a.counters) HOPCHK(ctx, hipMemcpy(c, a.counters, 16, hipMemcpyDeviceToHost));
-        ctx->stats.ms_sort = t0;
-        ctx->stats.ms_knn = t1;
-        ctx->stats.n = n;
-        ctx->stats.nodes_visited = (int64_t)c[0];
-        ctx->stats.leaves_scanned = (int64_t)c[1];
-        for (auto &e : ev) (void)hipEventDestroy(e);
+        HOPCHK(ctx, ev.create());
+        HOPCHK(ctx, hipEventRecord(ev.e[0], s));
     }
-    return HOP_OK;
+
+    // work description: subvolume order, first bucket of each, norms
+    std::vector<int32_t> order(n_sub);
+    for (int k = 0; k < n_sub; k++) order[k] = k;
+    if (ctx->tuning.largest_first)
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+            return off[x + 1] - off[x] > off[y + 1] - off[y];
+        });
+    std::vector<int64_t> item_off(n_sub + 1);
+    item_off[0] = 0;
+    for (int k = 0; k < n_sub; k++)
+        item_off[k + 1] = item_off[k] + hop_div_up(off[order[k] + 1] - off[order[k]], HOP_BUCKET);
+    std::vector<double> nrm(n_sub);
+    std::vector<float> nrm32(n_sub);
+    for (int k = 0; k < n_sub; k++) {
+        nrm[k] = norm_of(p, mean_density ? mean_density[k] : 0.0, off[k + 1] - off[k]);
+        nrm32[k] = (float)nrm[k];
+    }
+    const size_t n1 = (size_t)n_sub + 1;
+    size_t o_sub = 0, o_ord = o_sub + 8 * n1, o_item = (o_ord + 4 * n1 + 7) & ~(size_t)7;
+    size_t o_nrm = o_item + 8 * n1, o_n32 = o_nrm + 8 * n1, o_q = (o_n32 + 4 * n1 + 63) & ~(size_t)63;
+    size_t o_done = o_q + 64, bytes = o_done + 4 * n1;
+    std::vector<char> host(bytes, 0);
+    std::memcpy(host.data() + o_sub, off, 8 * n1);
+    std::memcpy(host.data() + o_ord, order.data(), 4 * (size_t)n_sub);
+    std::memcpy(host.data() + o_item, item_off.data(), 8 * n1);
+    std::memcpy(host.data() + o_nrm, nrm.data(), 8 * (size_t)n_sub);
+    std::memcpy(host.data() + o_n32, nrm32.data(), 4 * (size_t)n_sub);
+    HOPTRY(hop_reserve(ctx, ctx->batch_tab, bytes));
+    char *tab = (char *)ctx->batch_tab.ptr;
+    HOPCHK(ctx, hipMemcpyAsync(tab, host.data(), bytes, hipMemcpyHostToDevice, s));
+    HOPCHK(ctx, hipStreamSynchronize(s));  // `host` goes out of scope
+    const int64_t *sub_off = (const int64_t *)(tab + o_sub);
+    *sub_off_dev = (int64_t *)(tab + o_sub);
+
+    // 1. keys (subvolume, Morton) and sort
+    int sub_bits = 1;
+    while (((int64_t)1 << sub_bits) < n_sub) sub_bits++;
+    HOPTRY(hop_reserve(ctx, ctx->keys_a, (size_t)n * 8));
+    HOPTRY(hop_reserve(ctx, ctx->keys_b, (size_t)n * 8));
+    HOPTRY(hop_reserve(ctx, ctx->vals_a, (size_t)n * 4));
+    HOPTRY(hop_reserve(ctx, ctx->vals_b, (size_t)n * 4));
+    uint64_t *keys = (uint64_t *)ctx->keys_a.ptr;
+    uint32_t *perm = (uint32_t *)ctx->vals_a.ptr;
+    k_morton_batch<<<hop_grid(n, 256), 256, 0, s>>>(pos, n, glim, sub_off, n_sub, sub_bits, keys,
+                                                    perm, dflags);
+    HOPCHK(ctx, hipGetLastError());
+    HOPTRY(hop_radix_sort(ctx, keys, perm, (uint64_t *)ctx->keys_b.ptr, (uint32_t *)ctx->vals_b.ptr,
+                          n, 64, s));
+
+    // 2. one tree over the whole batch; the walk stays inside a subvolume
+    TreeLevels lv;
+    SortedRec *recs = nullptr;
+    NodeBox *boxes = nullptr;
+    HOPTRY(build_tree(ctx, n, pos, nullptr, glim, s, lv, recs, boxes));
+    if (ctx->profiling) HOPCHK(ctx, hipEventRecord(ev.e[1], s));
+
+    // 3. persistent kNN + density over all buckets of all subvolumes
+    KnnArgs a;
+    base_args(ctx, a, n, p, recs, boxes, lv, density, nbr, nullptr);
+    HOPTRY(start_counters(ctx, a, s));
+    BatchArgs b{};
+    b.sub_off = sub_off;
+    b.order = (const int32_t *)(tab + o_ord);
+    b.item_off = (const int64_t *)(tab + o_item);
+    b.norm = (const double *)(tab + o_nrm);
+    b.norm32 = (const float *)(tab + o_n32);
+    b.queue = (uint32_t *)(tab + o_q);
+    b.done = (uint32_t *)(tab + o_done);
+    b.n_items = item_off[n_sub];
+    b.n_sub = n_sub;
+    b.xcd_queues = ctx->tuning.xcd_queues ? 1 : 0;
+    int waves = ctx->tuning.persistent_waves > 0 ? ctx->tuning.persistent_waves : 4 * ctx->n_cu;
+    if (waves < 8) waves = 8;
+    if (periodic) k_knn_batch<true><<<waves, 64, 0, s>>>(a, b);
+    else k_knn_batch<false><<<waves, 64, 0, s>>>(a, b);
+    HOPCHK(ctx, hipGetLastError());
+    if (ctx->profiling) HOPCHK(ctx, hipEventRecord(ev.e[2], s));
+
+    // every bucket of every subvolume must have been processed once
+    std::vector<uint32_t> done(n_sub);
+    HOPCHK(ctx, hipMemcpyAsync(done.data(), b.done, 4 * (size_t)n_sub, hipMemcpyDeviceToHost, s));
+    HOPCHK(ctx, hipStreamSynchronize(s));
+    for (int k = 0; k < n_sub; k++)
+        if ((int64_t)done[k] != hop_div_up(off[k + 1] - off[k], HOP_BUCKET))
+            return hop_fail(ctx, HOP_ERR_ARG, "batched kNN left work undone");
+    return finish_stats(ctx, ev, a, n);
 }

@@ -377,6 +377,36 @@ __global__ void k_group(int64_t n, const int32_t *__restrict__ chain_of, int32_t
     group[i] = g;
 }
 
+// subvolume of chain c: the largest s < n_sub with chain_base[s] <= c
+__device__ __forceinline__ int sub_of_chain(const int32_t *__restrict__ cbase, int n_sub, int32_t c)
+{
+    int lo = 0, hi = n_sub;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cbase[mid] <= c) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_key_sub(int64_t G, const uint32_t *__restrict__ vals,
+                          const int32_t *__restrict__ cbase, int n_sub, uint64_t *__restrict__ keys)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= G) return;
+    keys[t] = (uint64_t)sub_of_chain(cbase, n_sub, (int32_t)vals[t]);
+}
+
+__global__ void k_group_first(int64_t G, const uint32_t *__restrict__ vals,
+                              const int32_t *__restrict__ cbase, int n_sub,
+                              int32_t *__restrict__ gfirst)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= G) return;
+    const int sv = sub_of_chain(cbase, n_sub, (int32_t)vals[t]);
+    if (t == 0 || sub_of_chain(cbase, n_sub, (int32_t)vals[t - 1]) != sv) gfirst[sv] = (int32_t)t;
+}
+
 __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -409,7 +439,8 @@ inline int64_t pow2ceil(int64_t v)
 int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
                    const int32_t *root, const int32_t *chain_of, int32_t n_chains,
                    const int32_t *tk, const uint8_t *padded, const hop_params *p, int32_t *group,
-                   int32_t *n_groups, hop_group_info *groups, hipStream_t s)
+                   int32_t *n_groups, hop_group_info *groups, const int32_t *chain_base,
+                   int32_t n_sub, int32_t *group_first, hipStream_t s)
 {
     uint32_t *dflags = (uint32_t *)ctx->flags.ptr;
     uint32_t *dcnt = dflags + 4;  // [0] edges, [1] msf edges, [2] halos
@@ -558,6 +589,18 @@ int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *de
         HOPTRY(hop_radix_sort(ctx, keys, vals, tkeys, tvals, G, 64, s));
         k_key_count<<<hop_grid(G, 256), 256, 0, s>>>(G, vals, hcount, keys);
         HOPTRY(hop_radix_sort(ctx, keys, vals, tkeys, tvals, G, 32, s));
+        if (chain_base) {
+            // a batch: subvolume first, so each subvolume's groups are contiguous
+            int sub_bits = 1;
+            while (((int64_t)1 << sub_bits) < n_sub) sub_bits++;
+            k_key_sub<<<hop_grid(G, 256), 256, 0, s>>>(G, vals, chain_base, n_sub, keys);
+            HOPCHK(ctx, hipGetLastError());
+            HOPTRY(hop_radix_sort(ctx, keys, vals, tkeys, tvals, G, sub_bits, s));
+        }
+    }
+    if (chain_base && group_first && G > 0) {
+        k_group_first<<<hop_grid(G, 256), 256, 0, s>>>(G, vals, chain_base, n_sub, group_first);
+        HOPCHK(ctx, hipGetLastError());
     }
     if (G > 0)
         k_number<<<hop_grid(G, 256), 256, 0, s>>>(G, vals, hcount, hpeak, hptk, tk2j, num, groups);

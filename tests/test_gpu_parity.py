@@ -197,15 +197,15 @@ def test_degenerate_reported(ctx):
     assert e.value.code == -3
 
 
-def test_coarse_leaf_ranges_parity(orc, monkeypatch):
+def test_coarse_leaf_ranges_parity(orc):
     """A tiny frontier capacity stops the breadth-first walk near the root,
     so every bucket streams whole subtrees; results must not change."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1001_3411_amd import HopContext
-    monkeypatch.setenv("HOP_FRONT_CAP", "2")
     c = HopContext(0)
+    c.set_tuning(front_cap=2)
     try:
         for p in (synth.config(1), synth.padded_subvolume(9000, 41)):
             pr = p.padded is not None
