@@ -3,9 +3,15 @@
 One step = hop_density (Morton sort, tree, kNN + FP64 density) + hop_link +
 hop_groups + hop_merge over the 134,217,728-particle clustered box (40,000
 NFW clumps, 30% uniform background), inputs resident in HBM.  Prints one
-JSON line (see the design doc for the roofline accounting).
+JSON line with the roofline of the kNN kernel and the CPU oracle's rate.
 
     python bench.py [--steps K] [--warmup W] [--config 5] [--no-cpu]
+    python bench.py --workload batch64 [--tune-cache PATH]
+
+The batch64 workload runs the 64 padded subvolumes (about 18M particles,
+lognormal sizes) through one hop_run_batch call per step, after the
+autotuner has picked its launch settings, and times 64 sequential
+single-subvolume runs of the same data beside it.
 """
 from __future__ import annotations
 
@@ -51,19 +57,16 @@ def cpu_baseline(p, budget_frac=4):
                       f"boundaries, merge, labels), {dt:.1f} s, {r.n_groups} groups"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=5)
-    ap.add_argument("--no-cpu", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              f"decomposition is described in DESIGN.md but not built.", file=sys.stderr)
-        sys.exit(2)
+def knn_roofline(n, knn_ms, kernel, value):
+    knn_s = knn_ms / 1e3
+    achieved = KNN_BYTES_PER_PARTICLE * n / knn_s / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": None, "kernel_ms": round(knn_ms, 3),
+            "path_frac": round(PATH_BYTES_PER_PARTICLE * value / 1e9 / HBM_PEAK_GBS, 5)}
 
+
+def bench_box(args):
     import numpy as np
     import torch
 
@@ -107,13 +110,7 @@ def main():
     groups, chains = out["n_groups"], out["n_chains"]
     log(f"{args.steps} steps: {ms_step:.2f} ms/step, knn {np.mean(knn_ms):.2f} ms, "
         f"sort+tree {np.mean(sort_ms):.2f} ms, groups={groups} chains={chains}")
-
-    knn_s = float(np.mean(knn_ms)) / 1e3
-    achieved = KNN_BYTES_PER_PARTICLE * n / knn_s / 1e9
-    roofline = {"bound": "hbm", "kernel": "k_knn_density", "achieved": round(achieved, 2),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": None, "kernel_ms": round(knn_s * 1e3, 3),
-                "path_frac": round(PATH_BYTES_PER_PARTICLE * value / 1e9 / HBM_PEAK_GBS, 5)}
+    roofline = knn_roofline(n, float(np.mean(knn_ms)), "k_knn_density", value)
     del out
     cpu = None
     if not args.no_cpu:
@@ -122,7 +119,7 @@ def main():
             log(f"cpu baseline: {cpu['value']:.3g} particles/s on {cpu['cores']} threads")
         except Exception as e:  # the baseline is reported, never required
             log(f"cpu baseline failed: {e}")
-    line = {"metric": "HOP particles/sec at 134M clustered (plain vs learned-radius); % HBM roofline",
+    return {"metric": "HOP particles/sec at 134M clustered (plain vs learned-radius); % HBM roofline",
             "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -130,6 +127,129 @@ def main():
                        "n_merge": prm.n_merge, "k_store": prm.k_store, "periodic": p.periodic,
                        "search": "plain", "groups": groups, "chains": chains},
             "roofline": roofline, "cpu_baseline": cpu}
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1001_3411_amd import HopContext, HopParams
+    from paper_1001_3411_amd.autotune import tune_batch
+
+    t0 = time.perf_counter()
+    subs = synth.config(4)
+    off = np.concatenate([[0], np.cumsum([q.n for q in subs])]).astype(np.int64)
+    n = int(off[-1])
+    log(f"generated {len(subs)} subvolumes, n={n} in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(np.concatenate([q.pos for q in subs]).view(np.int32)).to(dev)
+    padded = torch.from_numpy(np.concatenate([q.padded for q in subs])).to(dev)
+    md = [q.mean_density for q in subs]
+    prm = HopParams(periodic=False, padded_rules=True)
+    ctx = HopContext(0)
+
+    t0 = time.perf_counter()
+    tune = tune_batch(ctx, pos, off, prm, padded=padded, mean_density=md,
+                      cache_path=args.tune_cache)
+    log(f"tuning {'(cached) ' if tune['cached'] else ''}{tune['tuning']} "
+        f"{tune['ms']:.1f} ms in {time.perf_counter() - t0:.1f}s")
+
+    def batched():
+        return ctx.run_batch(pos, off, prm, padded=padded, mean_density=md)
+
+    def sequential():
+        outs = []
+        for s in range(len(subs)):
+            a, b = int(off[s]), int(off[s + 1])
+            q = HopParams(periodic=False, padded_rules=True, mean_density=md[s])
+            outs.append(ctx.run(pos[a:b], q, padded=padded[a:b]))
+        return outs
+
+    for w in range(args.warmup):
+        out = batched()
+        seq = sequential()
+        torch.cuda.synchronize()
+        same = all(torch.equal(out["group"][int(off[s]):int(off[s + 1])], seq[s]["group"])
+                   and torch.equal(out["nbr"][int(off[s]):int(off[s + 1])], seq[s]["nbr"])
+                   for s in range(len(subs)))
+        log(f"warmup {w}: groups={sum(out['n_groups'])}, batched == sequential: {same}")
+        if not same:
+            raise SystemExit("batched and sequential results differ")
+        del out, seq
+
+    ctx.set_profiling(1)
+    knn_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = batched()
+        knn_ms.append(ctx.stats()["ms_knn"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.set_profiling(0)
+    groups = sum(out["n_groups"])
+    del out
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        seq = sequential()
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t1
+    del seq
+    ms_step = dt * 1e3 / args.steps
+    ms_seq = dt_seq * 1e3 / args.steps
+    value = n / (dt / args.steps)
+    log(f"{args.steps} steps: batched {ms_step:.2f} ms/step (kNN {np.mean(knn_ms):.2f} ms), "
+        f"sequential {ms_seq:.2f} ms/step")
+    cpu = None
+    if not args.no_cpu:
+        try:
+            import oracle
+            k, t_cpu, done = 0, 0.0, 0
+            while k < len(subs) and t_cpu < 10.0:
+                q = subs[k]
+                t2 = time.perf_counter()
+                oracle.run(q.pos, periodic=False, mean_density=q.mean_density, padded=q.padded,
+                           padded_rules=True)
+                t_cpu += time.perf_counter() - t2
+                done += q.n
+                k += 1
+            cpu = {"value": done / t_cpu, "unit": "particles/s", "cores": oracle.num_threads(),
+                   "kind": "oracle",
+                   "sample": f"the first {k} subvolumes ({done} particles), whole pipeline "
+                             f"each, {t_cpu:.1f} s"}
+        except Exception as e:
+            log(f"cpu baseline failed: {e}")
+    return {"metric": "HOP particles/sec, 64 padded subvolumes in one batched call",
+            "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "batch64_subvolumes", "n": n, "n_sub": len(subs),
+                       "periodic": False, "padded_rules": True, "groups": groups,
+                       "tuning": tune["tuning"]},
+            "sequential": {"ms_per_step": ms_seq, "value": n / (dt_seq / args.steps),
+                           "launches": "64 x (hop_density, hop_link, hop_groups, hop_merge)"},
+            "speedup_vs_sequential": ms_seq / ms_step,
+            "roofline": knn_roofline(n, float(np.mean(knn_ms)), "k_knn_batch", value),
+            "cpu_baseline": cpu}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=5)
+    ap.add_argument("--workload", choices=["box", "batch64"], default="box")
+    ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              f"decomposition is described in the design notes but not built.", file=sys.stderr)
+        sys.exit(2)
+    line = bench_batch(args) if args.workload == "batch64" else bench_box(args)
     print(json.dumps(line), flush=True)
 
 
