@@ -55,6 +55,8 @@ extern "C" {
 #define HOP_PERIODIC       0x1u /* whole periodic box: minimum-image distances            */
 #define HOP_DENSITY_FP32   0x2u /* FP32 density arithmetic (the FP64 path is the default) */
 #define HOP_PADDED_RULES   0x4u /* section 3.1 rules for padded particles                 */
+#define HOP_LEARNED_RADIUS 0x8u /* hop_density: search radius from the loaded model,       */
+                                /* exact fallback (results unchanged)                      */
 
 /*
  * Parameters (section 4.1 and Table 2 of the paper).  Constraints:
@@ -263,6 +265,74 @@ typedef struct hop_tuning {
 int hop_set_tuning(hop_ctx *ctx, const hop_tuning *t);
 int hop_get_tuning(const hop_ctx *ctx, hop_tuning *t);
 
+/*
+ * Learned search radius.  The paper searches a fixed number of neighbours
+ * per particle; this extension predicts each particle's search radius from
+ * the particle counts of the 3x3x3 cells around its cell, so that the kNN
+ * walk can prune with it from the start.  The prediction only prunes: a
+ * particle whose n_dens-1 nearest others all lie within its radius keeps
+ * the list found; every other particle ("miss") is searched again without
+ * the radius.  Outputs are identical with and without the flag.
+ *
+ * Cells have side 2^cell_bits grid units.  Features of a particle: the 27
+ * values log(1 + count) of the cells (cz+dz, cy+dy, cx+dx), dz outermost,
+ * each of dz, dy, dx running -1, 0, 1 (periodic wrap under HOP_PERIODIC,
+ * count 0 outside otherwise).  Target: log(r / 2^cell_bits), r the distance
+ * to the particle's n_dens-th list entry.  The network maps the features to
+ * the target: 27 -> 64 -> 64 -> 1 with ReLU after the hidden layers; its
+ * parameters are one FP32 vector of HOP_MLP_PARAMS numbers in the order
+ * W1 [27][64] (input-major), b1 [64], W2 [64][64], b2 [64], W3 [64], b3 [1].
+ */
+#define HOP_MLP_PARAMS      6017
+#define HOP_RADIUS_MLP      1  /* the network, BF16 weights, FP32 accumulation      */
+#define HOP_RADIUS_ANALYTIC 2  /* no network: the radius whose ball holds n_dens
+                                  particles at the 27 cells' mean density          */
+
+/* Cell side bits hop_density uses for n particles: cells of side
+   2^cell_bits hold `occupancy` particles on average (between 2 and 2^9 cells
+   per axis).  Host-only; -1 on bad arguments. */
+int hop_radius_cell_bits(int64_t n, uint32_t grid_bits, float occupancy);
+
+/* Features [n][27] (and, if target is non-NULL, targets [n] from the
+   neighbour lists nbr [n][k_store], which need k_store = n_dens) for cells
+   of side 2^cell_bits; at most 2^9 cells per axis.  Synchronises. */
+int hop_radius_dataset(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int32_t *nbr,
+                       const hop_params *p, int32_t cell_bits, float *feats, float *target,
+                       void *stream);
+
+/* Mean squared error of the network w (device FP32 [HOP_MLP_PARAMS]) over
+   `batch` rows of (feats, target), rows idx[0..batch) (device) or the
+   first `batch` rows when idx is NULL, and its gradient grad
+   [HOP_MLP_PARAMS] (device); loss (device, 1 float) may be NULL.  FP32,
+   deterministic (fixed summation order).  Synchronises. */
+int hop_mlp_grad(hop_ctx *ctx, int64_t n_samples, const float *feats, const float *target,
+                 const int32_t *idx, int32_t batch, const float *w, float *grad, float *loss,
+                 void *stream);
+
+/* `steps` Adam steps (Kingma & Ba, bias-corrected) of the mean squared
+   error, step t using rows idx[t*batch .. (t+1)*batch) (device; NULL = the
+   first `batch` rows every step).  w, m, v (device FP32
+   [HOP_MLP_PARAMS]) are updated in place; the first step is number
+   first_step (>= 1) for the bias correction; loss (device [steps] or NULL)
+   receives each step's loss before its update.  Synchronises. */
+int hop_mlp_train(hop_ctx *ctx, int64_t n_samples, const float *feats, const float *target,
+                  const int32_t *idx, int32_t steps, int32_t batch, int32_t first_step, float lr,
+                  float beta1, float beta2, float eps, float *w, float *m, float *v, float *loss,
+                  void *stream);
+
+/* Loads the radius model used under HOP_LEARNED_RADIUS: kind 1 (w = device
+   FP32 parameters, rounded to BF16 to nearest even) or 2 (w ignored), 0 to
+   unload.  The search radius of a cell is 2^cell_bits * exp(prediction +
+   margin); hop_density picks cell_bits so that cells hold `occupancy`
+   particles on average.  Synchronises. */
+int hop_radius_load(hop_ctx *ctx, int32_t kind, const float *w, float margin, float occupancy,
+                    void *stream);
+
+/* The loaded model's prediction (log(r / side), margin not added) for rows
+   of features [rows][27] (device) into out [rows] (device).  Synchronises. */
+int hop_radius_predict(hop_ctx *ctx, int64_t rows, const float *feats, int32_t n_dens, float *out,
+                       void *stream);
+
 /* Synchronises `stream` and reports any error the device recorded since the
    last synchronising call (see the conventions above). */
 int hop_sync(hop_ctx *ctx, void *stream);
@@ -270,10 +340,13 @@ int hop_sync(hop_ctx *ctx, void *stream);
 /* Per-call statistics of the last hop_density on this context. */
 typedef struct hop_stats {
     double ms_sort;         /* Morton sort + tree build                          */
-    double ms_knn;          /* kNN + density kernel                              */
+    double ms_knn;          /* kNN + density kernel(s), fallback pass included   */
     int64_t n;              /* particles                                          */
     int64_t nodes_visited;  /* tree nodes tested, summed over waves (0 if off)   */
     int64_t leaves_scanned; /* leaves whose points were tested                   */
+    double ms_radius;       /* HOP_LEARNED_RADIUS: cell counts + per-cell model  */
+    int64_t misses;         /* HOP_LEARNED_RADIUS: particles searched again      */
+    int64_t redo_buckets;   /* HOP_LEARNED_RADIUS: buckets of the fallback pass  */
 } hop_stats;
 
 /* Profiling bits (default 0): 1 = time the sort/tree and kNN stages of

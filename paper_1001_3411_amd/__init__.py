@@ -13,7 +13,8 @@ from dataclasses import dataclass
 
 __all__ = [
     "LIB_PATH", "load", "HopParams", "HopError", "HopContext", "HOP_PERIODIC",
-    "HOP_DENSITY_FP32", "HOP_PADDED_RULES", "exported_symbols",
+    "HOP_DENSITY_FP32", "HOP_PADDED_RULES", "HOP_LEARNED_RADIUS", "HOP_RADIUS_MLP",
+    "HOP_RADIUS_ANALYTIC", "HOP_MLP_PARAMS", "exported_symbols",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -21,6 +22,10 @@ LIB_PATH = os.path.join(HERE, "libhop.so")
 
 HOP_PERIODIC = 0x1
 HOP_DENSITY_FP32 = 0x2
+HOP_LEARNED_RADIUS = 0x8
+HOP_RADIUS_MLP = 1
+HOP_RADIUS_ANALYTIC = 2
+HOP_MLP_PARAMS = 6017
 HOP_PADDED_RULES = 0x4
 
 ERRORS = {-1: "HOP_ERR_ARG", -2: "HOP_ERR_RANGE", -3: "HOP_ERR_DEGENERATE",
@@ -47,7 +52,8 @@ class _GroupInfo(C.Structure):
 
 class _Stats(C.Structure):
     _fields_ = [("ms_sort", C.c_double), ("ms_knn", C.c_double), ("n", C.c_int64),
-                ("nodes_visited", C.c_int64), ("leaves_scanned", C.c_int64)]
+                ("nodes_visited", C.c_int64), ("leaves_scanned", C.c_int64),
+                ("ms_radius", C.c_double), ("misses", C.c_int64), ("redo_buckets", C.c_int64)]
 
 
 @dataclass
@@ -66,11 +72,13 @@ class HopParams:
     periodic: bool = True
     padded_rules: bool = False
     density_fp32: bool = False
+    learned_radius: bool = False
 
     def c(self) -> _Params:
         flags = (HOP_PERIODIC if self.periodic else 0) | \
                 (HOP_PADDED_RULES if self.padded_rules else 0) | \
-                (HOP_DENSITY_FP32 if self.density_fp32 else 0)
+                (HOP_DENSITY_FP32 if self.density_fp32 else 0) | \
+                (HOP_LEARNED_RADIUS if self.learned_radius else 0)
         return _Params(self.n_dens, self.n_hop, self.n_merge, self.k_store, self.delta_outer,
                        self.delta_saddle, self.delta_peak, self.mean_density, self.grid_bits,
                        flags)
@@ -108,6 +116,14 @@ def load():
                             C.POINTER(i32), vp, vp]
     L.hop_run_batch.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(_Params), vp, vp, vp, vp, vp,
                                 vp, vp, vp, vp, vp, vp]
+    f32 = C.c_float
+    L.hop_radius_cell_bits.argtypes = [i64, C.c_uint32, f32]
+    L.hop_radius_dataset.argtypes = [vp, i64, vp, vp, C.POINTER(_Params), i32, vp, vp, vp]
+    L.hop_mlp_grad.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp, vp]
+    L.hop_mlp_train.argtypes = [vp, i64, vp, vp, vp, i32, i32, i32, f32, f32, f32, f32, vp, vp,
+                                vp, vp, vp]
+    L.hop_radius_load.argtypes = [vp, i32, vp, f32, f32, vp]
+    L.hop_radius_predict.argtypes = [vp, i64, vp, i32, vp, vp]
     L.hop_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     L.hop_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     L.hop_sync.argtypes = [vp, vp]
@@ -311,6 +327,58 @@ class HopContext:
         out["g_peak_dens"] = t[:, 2].contiguous().view(torch.float64)
         out.update(n_chains=nch.tolist(), n_groups=ngr.tolist(), group_off=goff.tolist(),
                    offsets=off.tolist())
+        return out
+
+    # -- learned search radius ----------------------------------------------
+    def radius_dataset(self, pos, params: HopParams, cell_bits: int, nbr=None, stream=None):
+        """Features [n][27] and (with nbr) targets [n] as float32 tensors."""
+        torch = self._torch
+        pos = self._dev(pos, torch.int32).view(torch.int32)
+        n = pos.shape[0]
+        feats = torch.empty((n, 27), dtype=torch.float32, device=pos.device)
+        target = torch.empty(n, dtype=torch.float32, device=pos.device) if nbr is not None else None
+        cp = params.c()
+        self._check(self.lib.hop_radius_dataset(self.h, n, _ptr(pos), _ptr(nbr), C.byref(cp),
+                                                int(cell_bits), _ptr(feats), _ptr(target),
+                                                self._stream(stream)))
+        return feats, target
+
+    def mlp_grad(self, feats, target, w, batch=None, idx=None, stream=None):
+        """(gradient [6017], loss) of the mean squared error over `batch` rows."""
+        torch = self._torch
+        if idx is not None:
+            idx = idx.to(device=feats.device, dtype=torch.int32).contiguous()
+            batch = idx.numel()
+        batch = int(batch if batch is not None else feats.shape[0])
+        grad = torch.empty(HOP_MLP_PARAMS, dtype=torch.float32, device=feats.device)
+        loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+        self._check(self.lib.hop_mlp_grad(self.h, feats.shape[0], _ptr(feats), _ptr(target),
+                                          _ptr(idx), batch, _ptr(w), _ptr(grad), _ptr(loss),
+                                          self._stream(stream)))
+        return grad, float(loss.item())
+
+    def mlp_train(self, feats, target, w, m, v, idx, steps, batch, first_step=1, lr=1e-3,
+                  beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        """Adam steps in place on w, m, v; returns the per-step losses."""
+        torch = self._torch
+        loss = torch.empty(max(int(steps), 1), dtype=torch.float32, device=feats.device)
+        if idx is not None:
+            idx = idx.to(device=feats.device, dtype=torch.int32).contiguous()
+        self._check(self.lib.hop_mlp_train(self.h, feats.shape[0], _ptr(feats), _ptr(target),
+                                           _ptr(idx), int(steps), int(batch), int(first_step),
+                                           lr, beta1, beta2, eps, _ptr(w), _ptr(m), _ptr(v),
+                                           _ptr(loss), self._stream(stream)))
+        return loss[:int(steps)]
+
+    def radius_load(self, kind, w=None, margin=0.0, occupancy=8.0, stream=None):
+        self._check(self.lib.hop_radius_load(self.h, int(kind), _ptr(w), float(margin),
+                                             float(occupancy), self._stream(stream)))
+
+    def radius_predict(self, feats, n_dens=64, stream=None):
+        torch = self._torch
+        out = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
+        self._check(self.lib.hop_radius_predict(self.h, feats.shape[0], _ptr(feats), int(n_dens),
+                                                _ptr(out), self._stream(stream)))
         return out
 
     def set_tuning(self, **kw):

@@ -85,7 +85,7 @@ int hop_check_params(hop_ctx *ctx, int64_t n, const hop_params *p)
         if (!std::isfinite(v) || v < 0) return hop_fail(ctx, HOP_ERR_ARG, "thresholds must be finite and >= 0");
     if (!std::isfinite(p->mean_density) || p->mean_density < 0)
         return hop_fail(ctx, HOP_ERR_ARG, "mean_density must be finite and >= 0");
-    if (p->flags & ~(HOP_PERIODIC | HOP_DENSITY_FP32 | HOP_PADDED_RULES))
+    if (p->flags & ~(HOP_PERIODIC | HOP_DENSITY_FP32 | HOP_PADDED_RULES | HOP_LEARNED_RADIUS))
         return hop_fail(ctx, HOP_ERR_ARG, "unknown flag");
     if (n < p->n_dens) return hop_fail(ctx, HOP_ERR_ARG, "need n >= n_dens");
     if (n >= ((int64_t)1 << 31) - 64) return hop_fail(ctx, HOP_ERR_ARG, "need n < 2^31");
@@ -156,7 +156,8 @@ void hop_ctx_destroy(hop_ctx *ctx)
                       &ctx->recs, &ctx->boxes, &ctx->tk, &ctx->tk2j, &ctx->flags,
                       &ctx->work_a, &ctx->work_b, &ctx->work_c, &ctx->work_d, &ctx->work_e,
                       &ctx->work_f, &ctx->hash_keys, &ctx->hash_vals, &ctx->edges_lo,
-                      &ctx->edges_hi, &ctx->edges_s, &ctx->batch_tab, &ctx->batch_aux};
+                      &ctx->edges_hi, &ctx->edges_s, &ctx->batch_tab, &ctx->batch_aux,
+                      &ctx->cell_counts, &ctx->cell_r, &ctx->radius_w, &ctx->mlp_part, &ctx->miss};
     for (DevBuf *b : bufs)
         if (b->ptr) hipFree(b->ptr);
     if (ctx->hflags) hipHostFree(ctx->hflags);

@@ -105,6 +105,8 @@ extern "C" int hop_run_batch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets
         return hop_fail(ctx, HOP_ERR_ARG, "pos and every per-particle output must be non-NULL");
     if (offsets[0] != 0) return hop_fail(ctx, HOP_ERR_ARG, "offsets[0] must be 0");
     if (!p) return hop_fail(ctx, HOP_ERR_ARG, "params is NULL");
+    if (p->flags & HOP_LEARNED_RADIUS)
+        return hop_fail(ctx, HOP_ERR_ARG, "HOP_LEARNED_RADIUS is not available for batches");
     for (int k = 0; k < n_sub; k++) {
         if (offsets[k + 1] - offsets[k] < p->n_dens)
             return hop_fail(ctx, HOP_ERR_ARG, "subvolume " + std::to_string(k) + " has fewer than n_dens particles");

@@ -71,6 +71,12 @@ struct hop_ctx {
     DevBuf hash_keys, hash_vals;
     DevBuf edges_lo, edges_hi, edges_s;
     DevBuf batch_tab, batch_aux;  // batched launch: work description, per-subvolume bases
+    DevBuf cell_counts, cell_r;   // learned radius: particles and search radius per cell
+    DevBuf radius_w, mlp_part;    // BF16 model weights; training partial sums
+    DevBuf miss;                  // learned radius: per-bucket lanes to search again
+    int radius_kind = 0;          // HOP_RADIUS_* of the loaded model, 0 = none
+    float radius_margin = 0.0f;
+    float radius_occupancy = 8.0f;
     // pinned host mirror of the device counters
     int64_t *hflags = nullptr;
 
@@ -147,6 +153,12 @@ int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *de
 int hop_density_batch_impl(hop_ctx *ctx, int32_t n_sub, const int64_t *off, const uint32_t *pos,
                            const double *mean_density, const hop_params *p, double *density,
                            int32_t *nbr, int64_t **sub_off_dev, hipStream_t s);
+
+// Learned radius: cell side bits for n particles, and the per-cell search
+// radii of pos (cell counts, then the loaded model per cell).
+int hop_cell_bits(const hop_ctx *ctx, int64_t n, const hop_params *p);
+int hop_radius_cells(hop_ctx *ctx, int64_t n, const uint32_t *pos, const hop_params *p, hipStream_t s,
+                     const float **cell_r, int *cb, int *gb);
 
 static inline int64_t hop_div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static inline int hop_grid(int64_t items, int per_block)

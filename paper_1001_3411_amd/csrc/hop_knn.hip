@@ -157,6 +157,12 @@ struct KnnArgs {
     const int32_t *tk2j;
     uint32_t *dflags;
     unsigned long long *counters;  // [0] nodes tested, [1] leaves scanned (NULL = off)
+    // learned radius (NULL = off): search radius per cell of side 2^cell_bits,
+    // 2^cell_gb cells per axis; lanes whose list does not fit inside it are
+    // recorded in miss[bucket] and write nothing
+    const float *cell_r;
+    int cell_bits, cell_gb;
+    unsigned long long *miss;
 };
 
 // Work description of a batched launch (device arrays, see k_knn_batch).
@@ -372,11 +378,14 @@ __device__ __forceinline__ void rh_replace_root(RegHeap &H, uint64_t *heap, int 
 // one subvolume of a batch).  Candidates outside [plo, phi) are never
 // offered, and the walk never enters a subtree whose leaves lie outside it.
 // heap, stage and leaves are the wave's LDS buffers.
+// Only the lanes set in qmask are queries; the others still serve as
+// candidates.
 template <bool PERIODIC, bool IDS>
 __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, const int bcount,
                                            const int64_t plo, const int64_t phi,
                                            const double norm, const float norm32, uint64_t *heap,
-                                           SortedRec *stage, uint32_t *leaves)
+                                           SortedRec *stage, uint32_t *leaves, const uint64_t qmask,
+                                           const int64_t bucket_id)
 {
     // the walk's two frontier buffers live in the heap area until the heap
     // is filled
@@ -384,19 +393,27 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     uint32_t *front_b = front_a + kFrontLevel;
 
     const int lane = threadIdx.x;
-    const bool active = lane < bcount;
+    const bool active = lane < bcount && ((qmask >> lane) & 1ull);
     const int hs = a.hs;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const double G = a.gsize;
     const int64_t n_leaf_total = a.lv.cnt[0];
     unsigned long long n_nodes = 0, n_lv = 0;
 
-    if (active) stage[lane] = a.recs[b0 + lane];
+    if (lane < bcount) stage[lane] = a.recs[b0 + lane];
     __syncthreads();
-    const SortedRec me = stage[active ? lane : 0];
+    const SortedRec me = stage[lane < bcount ? lane : 0];
     const double qx = me.x, qy = me.y, qz = me.z;
     const uint32_t ux = (uint32_t)qx, uy = (uint32_t)qy, uz = (uint32_t)qz;
     const int32_t mytk = me.tk;
+    // squared search radius of a bounded (learned-radius) search
+    double rcap = 1.0e300;
+    if (a.cell_r && active) {
+        const int64_t c = ((int64_t)(uz >> a.cell_bits) << (2 * a.cell_gb)) |
+                          ((int64_t)(uy >> a.cell_bits) << a.cell_gb) | (int64_t)(ux >> a.cell_bits);
+        const double r = (double)a.cell_r[c];
+        rcap = r * r;
+    }
 
     // 1. seed the heap with the bucket's other particles (the first hs go
     //    straight into place, then one heapify) ...
@@ -421,7 +438,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         for (int q = 0; q < 4; q++) H.r1[q] = heap[(q + 1) * 64 + lane];
     }
     uint64_t tau_key = H.r0;
-    double tau = active ? key_d2(tau_key, a.shift) : -1.0;
+    double tau = active ? fmin(key_d2(tau_key, a.shift), rcap) : -1.0;
     // offer the particles of the staged batch whose bits are set
     auto insert_marked = [&](uint64_t pass, bool wrap) {
         while (__any(pass != 0)) {
@@ -434,7 +451,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
                 if (key < tau_key) {
                     rh_replace_root(H, heap, lane, hs, key);
                     tau_key = H.r0;
-                    tau = key_d2(tau_key, a.shift);
+                    tau = fmin(key_d2(tau_key, a.shift), rcap);
                 }
             }
         }
@@ -699,7 +716,15 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         atomicAdd(&a.counters[0], n_nodes);
         atomicAdd(&a.counters[1], n_lv);
     }
-    if (!active) return;
+    // a bounded search is exact for a lane whose whole list lies inside its
+    // radius; the other lanes are searched again without it
+    bool miss = false;
+    if (a.cell_r) {
+        miss = active && (H.r0 == ~0ull || key_d2(H.r0, a.shift) > rcap);
+        const uint64_t mm = __ballot(miss);
+        if (lane == 0 && mm) a.miss[bucket_id] = mm;
+    }
+    if (!active || miss) return;
 
     // sort the heap ascending in registers (bitonic network over 64 slots)
     uint64_t v[64];
@@ -835,7 +860,34 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     if (bucket >= a.n_buckets) return;
     const int64_t b0 = bucket * HOP_BUCKET;
     knn_bucket<PERIODIC, IDS>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n, a.norm,
-                              a.norm32, heap, stage, leaves);
+                              a.norm32, heap, stage, leaves, ~0ull, bucket);
+}
+
+// Fallback of a bounded search: the listed buckets again, without a radius,
+// for the lanes recorded in miss[bucket] only.
+template <bool PERIODIC, bool IDS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_redo(
+    KnnArgs a, const uint32_t *__restrict__ list, const unsigned long long *__restrict__ miss)
+{
+    __shared__ uint64_t heap[kHeapSlots * 64];
+    __shared__ SortedRec stage[64];
+    __shared__ uint32_t leaves[kLeafList];
+    const int64_t bucket = list[blockIdx.x];
+    const int64_t b0 = bucket * HOP_BUCKET;
+    knn_bucket<PERIODIC, IDS>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n, a.norm,
+                              a.norm32, heap, stage, leaves, miss[bucket], bucket);
+}
+
+// buckets with a recorded miss -> list; count the missed lanes
+__global__ void k_miss_list(int64_t n_buckets, const unsigned long long *__restrict__ miss,
+                            uint32_t *__restrict__ list, uint32_t *__restrict__ counts)
+{
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_buckets) return;
+    const unsigned long long m = miss[b];
+    if (!m) return;
+    list[atomicAdd(&counts[0], 1u)] = (uint32_t)b;
+    atomicAdd(&counts[1], (uint32_t)__popcll(m));
 }
 
 // A batch of independent subvolumes, one persistent wave per SIMD.  Work
@@ -877,7 +929,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         const int64_t b0 = plo + (item - b.item_off[lo]) * HOP_BUCKET;
         __syncthreads();
         knn_bucket<PERIODIC, false>(a, b0, (int)min((int64_t)HOP_BUCKET, phi - b0), plo, phi,
-                                    b.norm[sv], b.norm32[sv], heap, stage, leaves);
+                                    b.norm[sv], b.norm32[sv], heap, stage, leaves, ~0ull, 0);
         if (lane == 0) atomicAdd(&b.done[sv], 1u);
     }
 }
@@ -920,7 +972,7 @@ __global__ void k_morton_batch(const uint32_t *__restrict__ pos, int64_t n, uint
 
 // HIP events that are destroyed on every exit path
 struct Events {
-    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
     ~Events()
     {
         for (auto &x : e)
@@ -1017,13 +1069,23 @@ int finish_stats(hop_ctx *ctx, Events &ev, const KnnArgs &a, int64_t n)
 {
     if (!ctx->profiling) return HOP_OK;
     HOPCHK(ctx, hipEventSynchronize(ev.e[2]));
-    float t0 = 0, t1 = 0;
+    // e[0] start, e[1] tree built, e[3] radius model done (learned only),
+    // e[2] kNN done
+    float t0 = 0, t1 = 0, tr = 0;
     HOPCHK(ctx, hipEventElapsedTime(&t0, ev.e[0], ev.e[1]));
-    HOPCHK(ctx, hipEventElapsedTime(&t1, ev.e[1], ev.e[2]));
+    if (a.cell_r) {
+        HOPCHK(ctx, hipEventElapsedTime(&tr, ev.e[1], ev.e[3]));
+        HOPCHK(ctx, hipEventElapsedTime(&t1, ev.e[3], ev.e[2]));
+    } else {
+        HOPCHK(ctx, hipEventElapsedTime(&t1, ev.e[1], ev.e[2]));
+    }
     unsigned long long c[2] = {0, 0};
     if (a.counters) HOPCHK(ctx, hipMemcpy(c, a.counters, 16, hipMemcpyDeviceToHost));
     ctx->stats.ms_sort = t0;
     ctx->stats.ms_knn = t1;
+    ctx->stats.ms_radius = tr;
+    ctx->stats.misses = 0;
+    ctx->stats.redo_buckets = 0;
     ctx->stats.n = n;
     ctx->stats.nodes_visited = (int64_t)c[0];
     ctx->stats.leaves_scanned = (int64_t)c[1];
@@ -1081,11 +1143,19 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     HOPTRY(build_tree(ctx, n, pos, tk, glim, s, lv, recs, boxes));
     if (ctx->profiling) HOPCHK(ctx, hipEventRecord(ev.e[1], s));
 
-    // 3. kNN + density
+    // 3. kNN + density (bounded by the per-cell search radius if asked for)
     KnnArgs a;
     base_args(ctx, a, n, p, recs, boxes, lv, density, nbr, tk2j);
     a.norm = norm_of(p, p->mean_density, n);
     a.norm32 = (float)a.norm;
+    const bool learned = (p->flags & HOP_LEARNED_RADIUS) != 0;
+    if (learned) {
+        HOPTRY(hop_radius_cells(ctx, n, pos, p, s, &a.cell_r, &a.cell_bits, &a.cell_gb));
+        HOPTRY(hop_reserve(ctx, ctx->miss, (size_t)a.n_buckets * 8 + 4 * (size_t)a.n_buckets + 64));
+        a.miss = (unsigned long long *)ctx->miss.ptr;
+        HOPCHK(ctx, hipMemsetAsync(a.miss, 0, (size_t)a.n_buckets * 8, s));
+    }
+    if (ctx->profiling) HOPCHK(ctx, hipEventRecord(ev.e[3], s));
     HOPTRY(start_counters(ctx, a, s));
     const int64_t grid = a.xcd_chunk * 8;
     if (grid >= ((int64_t)1 << 31)) return hop_fail(ctx, HOP_ERR_ARG, "too many particles");
@@ -1097,8 +1167,36 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
         else k_knn_density<false, false><<<(int)grid, 64, 0, s>>>(a);
     }
     HOPCHK(ctx, hipGetLastError());
+    int64_t misses = 0, redo = 0;
+    if (learned) {
+        uint32_t *list = (uint32_t *)((char *)ctx->miss.ptr + (size_t)a.n_buckets * 8);
+        uint32_t *cnt = (uint32_t *)ctx->flags.ptr + 8;
+        HOPCHK(ctx, hipMemsetAsync(cnt, 0, 8, s));
+        k_miss_list<<<hop_grid(a.n_buckets, 256), 256, 0, s>>>(a.n_buckets, a.miss, list, cnt);
+        HOPCHK(ctx, hipGetLastError());
+        HOPCHK(ctx, hipMemcpyAsync(&ctx->hflags[8], cnt, 8, hipMemcpyDeviceToHost, s));
+        HOPCHK(ctx, hipStreamSynchronize(s));
+        const uint32_t *hc = (const uint32_t *)&ctx->hflags[8];
+        redo = hc[0];
+        misses = hc[1];
+        if (redo > 0) {
+            KnnArgs r = a;
+            r.cell_r = nullptr;
+            if (periodic) {
+                if (id) k_knn_redo<true, true><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
+                else k_knn_redo<true, false><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
+            } else {
+                if (id) k_knn_redo<false, true><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
+                else k_knn_redo<false, false><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
+            }
+            HOPCHK(ctx, hipGetLastError());
+        }
+    }
     if (ctx->profiling) HOPCHK(ctx, hipEventRecord(ev.e[2], s));
-    return finish_stats(ctx, ev, a, n);
+    HOPTRY(finish_stats(ctx, ev, a, n));
+    ctx->stats.misses = misses;
+    ctx->stats.redo_buckets = redo;
+    return HOP_OK;
 }
 
 int hop_density_batch_impl(hop_ctx *ctx, int32_t n_sub, const int64_t *off, const uint32_t *pos,

@@ -49,3 +49,15 @@ def test_no_cpu_fallback_in_binding():
     src = open(os.path.join(ROOT, "paper_1001_3411_amd", "__init__.py")).read()
     assert "oracle" not in src.replace("no fallback", "")
     assert "numpy" not in src.split("def _dev")[0]
+
+
+def test_radius_cell_bits_rule():
+    """Cells of side 2^cb hold about 8 particles on average."""
+    from paper_1001_3411_amd.radius import cell_bits_for
+    assert cell_bits_for(2 ** 24) == 14      # 128^3 cells
+    assert cell_bits_for(2 ** 27) == 13      # 256^3 cells
+    assert cell_bits_for(2 ** 15) == 17      # 16^3 cells
+    assert cell_bits_for(10, 21) == 20       # never fewer than 2 cells per axis
+    assert cell_bits_for(2 ** 40, 21) == 12  # never more than 2^9 per axis
+    with pytest.raises(ValueError):
+        cell_bits_for(0)
