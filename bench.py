@@ -5,8 +5,14 @@ hop_groups + hop_merge over the 134,217,728-particle clustered box (40,000
 NFW clumps, 30% uniform background), inputs resident in HBM.  Prints one
 JSON line with the roofline of the kNN kernel and the CPU oracle's rate.
 
-    python bench.py [--steps K] [--warmup W] [--config 5] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--config 5] [--no-cpu] [--search S]
     python bench.py --workload batch64 [--tune-cache PATH]
+
+--search compare (the default) also runs the same steps with the search
+radius predicted per cell -- by the network trained on the Zel'dovich box's
+own kNN radii, and by the analytic uniform-density estimate -- checks that
+every output is identical to the plain run's, and reports both beside the
+plain line; --search plain skips that.
 
 The batch64 workload runs the 64 padded subvolumes (about 18M particles,
 lognormal sizes) through one hop_run_batch call per step, after the
@@ -66,6 +72,37 @@ def knn_roofline(n, knn_ms, kernel, value):
             "path_frac": round(PATH_BYTES_PER_PARTICLE * value / 1e9 / HBM_PEAK_GBS, 5)}
 
 
+def radius_models(ctx, log_fn):
+    """Train the radius network on the 16.8M-particle Zel'dovich box's own
+    kNN radii; calibrate it and the analytic estimate for a 1% miss rate."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1001_3411_amd import HOP_RADIUS_ANALYTIC, HOP_RADIUS_MLP, HopParams
+    from paper_1001_3411_amd.radius import calibrate, cell_bits_for, train
+
+    t0 = time.perf_counter()
+    p3 = synth.config(3)
+    prm3 = HopParams(mean_density=p3.mean_density)
+    pos3 = torch.from_numpy(p3.pos.view(np.int32)).cuda()
+    _, nbr = ctx.density(pos3, prm3)
+    feats, target = ctx.radius_dataset(pos3, prm3, cell_bits_for(p3.n), nbr=nbr)
+    del nbr, pos3
+    w, losses = train(ctx, feats, target, steps=3000, batch=4096, seed=0)
+    m_mlp = calibrate(ctx, w, feats, target, miss_rate=0.01, kind=HOP_RADIUS_MLP)
+    m_an = calibrate(ctx, None, feats, target, miss_rate=0.01, kind=HOP_RADIUS_ANALYTIC)
+    del feats, target
+    torch.cuda.empty_cache()
+    log_fn(f"radius models from {p3.name} in {time.perf_counter() - t0:.1f}s: "
+           f"loss {losses[:50].mean():.3f} -> {losses[-50:].mean():.3f}, margins mlp {m_mlp:.3f} "
+           f"analytic {m_an:.3f}")
+    return {"mlp": (HOP_RADIUS_MLP, w, m_mlp), "analytic": (HOP_RADIUS_ANALYTIC, None, m_an),
+            "train": {"dataset": p3.name, "samples": p3.n, "steps": 3000, "batch": 4096,
+                      "loss_first": float(losses[:50].mean()),
+                      "loss_last": float(losses[-50:].mean())}}
+
+
 def bench_box(args):
     import numpy as np
     import torch
@@ -111,7 +148,54 @@ def bench_box(args):
     log(f"{args.steps} steps: {ms_step:.2f} ms/step, knn {np.mean(knn_ms):.2f} ms, "
         f"sort+tree {np.mean(sort_ms):.2f} ms, groups={groups} chains={chains}")
     roofline = knn_roofline(n, float(np.mean(knn_ms)), "k_knn_density", value)
-    del out
+    search = None
+    if args.search == "compare":
+        from dataclasses import replace
+        ref = {k: out[k] for k in ("nbr", "density", "hop", "group")}
+        del out
+        models = radius_models(ctx, log)
+        search = {"training": models.pop("train")}
+        for name in ("plain", "analytic", "mlp"):
+            q = prm
+            if name != "plain":
+                kind, w, margin = models[name]
+                ctx.radius_load(kind, w, margin)
+                q = replace(prm, learned_radius=True)
+            # counters: one untimed run
+            ctx.set_profiling(3)
+            o = ctx.run(pos, q, stream=stream)
+            st = ctx.stats()
+            same = all(torch.equal(o[k], ref[k]) for k in ref)
+            del o
+            ctx.set_profiling(1)
+            kms, rms = [], []
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for k in range(args.steps):
+                o = ctx.run(pos, q, stream=stream)
+                s2 = ctx.stats()
+                kms.append(s2["ms_knn"])
+                rms.append(s2["ms_radius"])
+                del o
+            torch.cuda.synchronize()
+            d1 = (time.perf_counter() - t1) / args.steps
+            ctx.set_profiling(0)
+            search[name] = {"ms_per_step": d1 * 1e3, "value": n / d1,
+                            "ms_knn": float(np.mean(kms)), "ms_radius": float(np.mean(rms)),
+                            "nodes_per_particle": st["nodes_visited"] / n,
+                            "leaf_batches_per_particle": st["leaves_scanned"] / n / 4,
+                            "misses": st["misses"], "miss_fraction": st["misses"] / n,
+                            "fallback_buckets": st["redo_buckets"], "identical_output": same}
+            if name != "plain":
+                search[name]["margin"] = models[name][2]
+            log(f"search {name}: {d1 * 1e3:.1f} ms/step, kNN {np.mean(kms):.1f} ms, "
+                f"misses {st['misses']}, identical {same}")
+            if not same:
+                raise SystemExit(f"{name} search changed the output")
+        ctx.radius_load(0)
+        del ref
+    else:
+        del out
     cpu = None
     if not args.no_cpu:
         try:
@@ -126,7 +210,7 @@ def bench_box(args):
             "config": {"workload": p.name, "n": n, "n_dens": prm.n_dens, "n_hop": prm.n_hop,
                        "n_merge": prm.n_merge, "k_store": prm.k_store, "periodic": p.periodic,
                        "search": "plain", "groups": groups, "chains": chains},
-            "roofline": roofline, "cpu_baseline": cpu}
+            "roofline": roofline, "cpu_baseline": cpu, "search_compare": search}
 
 
 def bench_batch(args):
@@ -244,6 +328,7 @@ def main():
     ap.add_argument("--workload", choices=["box", "batch64"], default="box")
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--search", choices=["compare", "plain"], default="compare")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "

@@ -36,6 +36,7 @@
 #include "hop_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <cstring>
 #include <vector>
 
@@ -491,6 +492,14 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     double tmax = tau;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, d));
+    {
+        // the same in every lane: make that visible to the compiler, so that
+        // the decisions taken from it are scalar branches
+        const long long tb = __double_as_longlong(tmax);
+        const int hi = __builtin_amdgcn_readfirstlane((int)(tb >> 32));
+        const int lo = __builtin_amdgcn_readfirstlane((int)(tb & 0xffffffff));
+        tmax = __longlong_as_double(((long long)hi << 32) | (uint32_t)lo);
+    }
 
     // groups of 8 consecutive lanes: box of their queries and largest bound,
     // held in scalar registers for the walk
@@ -639,6 +648,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         cy = 0.5 * ((double)bb.lo[1] + (double)bb.hi[1]);
         cz = 0.5 * ((double)bb.lo[2] + (double)bb.hi[2]);
     }
+    fastB = __builtin_amdgcn_readfirstlane(fastB ? 1 : 0) != 0;
     const int nbatch = (nleaf_total + 3) >> 2;
     auto range_len = [&](int r, int64_t *first) -> int {
         const uint32_t e = leaves[r];
@@ -669,44 +679,54 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         r = a.recs[idx];
         return true;
     };
-    SortedRec nxt;
-    bool nxt_ok = nbatch > 0 ? fetch(nxt) : false;
-    for (int bi = 0; bi < nbatch; bi++) {
-        SortedRec r = nxt;
-        const bool ok = nxt_ok;
-        if (ok) {
-            if (PERIODIC && fastB) {
-                const double half = 0.5 * G;
-                const double dx = r.x - cx, dy = r.y - cy, dz = r.z - cz;
-                r.x += dx > half ? -G : (dx < -half ? G : 0.0);
-                r.y += dy > half ? -G : (dy < -half ? G : 0.0);
-                r.z += dz > half ? -G : (dz < -half ? G : 0.0);
+    // one copy of the loop per distance form (FAST: images already chosen
+    // by the loading lane, or no periodicity), so the tests carry no branch
+    auto stream = [&](auto fast_tag) {
+        constexpr bool FAST = decltype(fast_tag)::value;
+        SortedRec nxt;
+        bool nxt_ok = nbatch > 0 ? fetch(nxt) : false;
+        for (int bi = 0; bi < nbatch; bi++) {
+            SortedRec r = nxt;
+            const bool ok = nxt_ok;
+            if (ok) {
+                if (PERIODIC && FAST) {
+                    const double half = 0.5 * G;
+                    const double dx = r.x - cx, dy = r.y - cy, dz = r.z - cz;
+                    r.x += dx > half ? -G : (dx < -half ? G : 0.0);
+                    r.y += dy > half ? -G : (dy < -half ? G : 0.0);
+                    r.z += dz > half ? -G : (dz < -half ? G : 0.0);
+                }
+            } else {
+                r.x = r.y = r.z = 1.0e30;  // never selected
+                r.j = -1;
+                r.tk = -1;
             }
-        } else {
-            r.x = r.y = r.z = 1.0e30;  // never selected
-            r.j = -1;
-            r.tk = -1;
-        }
-        __syncthreads();
-        stage[lane] = r;
-        __syncthreads();
-        for (int s = 0; s < 4 && cur_r < lcnt; s++) cursor_step(cur_r, cur_o);
-        if (bi + 1 < nbatch) nxt_ok = fetch(nxt);
-        if (!__any(ok)) continue;
-        n_lv += 4;
-        uint64_t pass = 0;
-        for (int k0 = 0; k0 < 64; k0 += 16) {
-            SortedRec pr[16];
+            __syncthreads();
+            stage[lane] = r;
+            __syncthreads();
+            for (int s = 0; s < 4 && cur_r < lcnt; s++) cursor_step(cur_r, cur_o);
+            if (bi + 1 < nbatch) nxt_ok = fetch(nxt);
+            if (!__any(ok)) continue;
+            n_lv += 4;
+            uint64_t pass = 0;
+            for (int k0 = 0; k0 < 64; k0 += 16) {
+                SortedRec pr[16];
 #pragma unroll
-            for (int k = 0; k < 16; k++) pr[k] = stage[k0 + k];
+                for (int k = 0; k < 16; k++) pr[k] = stage[k0 + k];
+                // (the bits go straight into the 64-bit mask: collecting them
+                // in a 16-bit word first gave wrong lists in the persistent
+                // batch kernel with this toolchain)
 #pragma unroll
-            for (int k = 0; k < 16; k++) {
-                const double d2 = (!PERIODIC || fastB) ? d2_direct(qx, qy, qz, pr[k]) : d2_wrap(qx, qy, qz, pr[k], G);
-                pass |= (uint64_t)((d2 <= tau && pr[k].tk != mytk) ? 1u : 0u) << (k0 + k);
+                for (int k = 0; k < 16; k++) {
+                    const double d2 = FAST ? d2_direct(qx, qy, qz, pr[k]) : d2_wrap(qx, qy, qz, pr[k], G);
+                    pass |= (uint64_t)((d2 <= tau && pr[k].tk != mytk) ? 1u : 0u) << (k0 + k);
+                }
             }
+            insert_marked(pass, PERIODIC && !FAST);
         }
-        insert_marked(pass, PERIODIC && !fastB);
-    }
+    };
+    if (!PERIODIC || fastB) stream(std::true_type{});
+    else stream(std::false_type{});
     // write the register levels back so the heap is whole in LDS
     heap[lane] = H.r0;
 #pragma unroll

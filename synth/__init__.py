@@ -197,7 +197,7 @@ def zeldovich_box(n_side: int, seed: int, n_clumps: int = 5000,
     del wk, white
     disp = np.empty((n, 3), dtype=np.float64)
     for ax, kk in enumerate((kx, ky, kz)):
-        comp = np.fft.irfftn(1j * kk * dk / k2, s=(ns, ns, ns))
+        comp = np.fft.irfftn(1j * kk * dk / k2, s=(ns, ns, ns), axes=(0, 1, 2))
         disp[:, ax] = comp.reshape(-1)
         del comp
     del dk
