@@ -15,7 +15,7 @@
 // (d^2, id) exactly (d^2 is an exact integer held in FP64); the heap's top
 // two levels sit in registers, the rest in LDS.  The search runs in three
 // passes:
-//   1. seed: the bucket's own particles and two Morton-neighbour buckets on
+//   1. seed: the bucket's own particles and three Morton-neighbour buckets on
 //      each side are offered, which gives every lane a finite bound;
 //   2. walk: a breadth-first descent of the tree, 64 child boxes tested per
 //      step against the boxes and bounds of 8 groups of 8 lanes; it stops at
@@ -131,6 +131,10 @@ __global__ void k_level_boxes(NodeBox *__restrict__ boxes, int64_t child_off, in
 // ---------------------------------------------------------------------------
 
 constexpr int kHeapMax = 63;   // n_dens - 1 <= 63
+#ifndef HOP_SEED_SIDES
+#define HOP_SEED_SIDES 3
+#endif
+constexpr int kSeedSides = HOP_SEED_SIDES;  // Morton-neighbour buckets seeded on each side
 constexpr int kHeapSlots = 65; // 4-ary heap: slots up to 4*15+4 are read
 
 struct KnnArgs {
@@ -457,14 +461,14 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
             }
         }
     };
-    // ... and offer the rest of the bucket (hs < 63 only) and two
+    // ... and offer the rest of the bucket (hs < 63 only) and kSeedSides
     //    Morton-neighbour buckets on each side (exact minimum image)
-    for (int side = 0; side < 5; side++) {
-        const int64_t nb0 = max(b0 + (side - 2) * HOP_BUCKET, plo);
-        const int64_t nb1 = side == 2 ? b0 + bcount : min(b0 + (side - 1) * HOP_BUCKET, phi);
+    for (int side = 0; side < 2 * kSeedSides + 1; side++) {
+        const int64_t nb0 = max(b0 + (side - kSeedSides) * HOP_BUCKET, plo);
+        const int64_t nb1 = side == kSeedSides ? b0 + bcount : min(b0 + (side - kSeedSides + 1) * HOP_BUCKET, phi);
         if (nb0 >= nb1) continue;
         const int ncnt = (int)(nb1 - nb0);
-        if (side == 2 && hs >= HOP_BUCKET - 1) continue;
+        if (side == kSeedSides && hs >= HOP_BUCKET - 1) continue;
         __syncthreads();
         if (lane < ncnt) stage[lane] = a.recs[nb0 + lane];
         __syncthreads();
@@ -478,15 +482,15 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
                 const int kk = k0 + k;
                 const double d2 = PERIODIC ? d2_wrap(qx, qy, qz, pr[k], G) : d2_direct(qx, qy, qz, pr[k]);
                 // own bucket: only the particles the fill did not take
-                const bool fresh = side != 2 || (kk != lane && kk - (kk > lane ? 1 : 0) >= hs);
+                const bool fresh = side != kSeedSides || (kk != lane && kk - (kk > lane ? 1 : 0) >= hs);
                 pass |= (uint64_t)((kk < ncnt && fresh && pr[k].tk != mytk && d2 <= tau) ? 1u : 0u) << kk;
             }
         }
         insert_marked(pass, PERIODIC);
     }
     // particles already offered by the seed, and the leaves of [plo, phi)
-    const int64_t seed_lo = max(b0 - 2 * HOP_BUCKET, plo);
-    const int64_t seed_hi = min(b0 + 3 * HOP_BUCKET, phi);
+    const int64_t seed_lo = max(b0 - kSeedSides * HOP_BUCKET, plo);
+    const int64_t seed_hi = min(b0 + (kSeedSides + 1) * HOP_BUCKET, phi);
     const int64_t leaf_lo = plo / HOP_LEAF, leaf_hi = (phi - 1) / HOP_LEAF;
 
     double tmax = tau;
