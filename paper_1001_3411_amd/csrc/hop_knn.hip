@@ -135,6 +135,10 @@ constexpr int kHeapMax = 63;   // n_dens - 1 <= 63
 #define HOP_SEED_SIDES 3
 #endif
 constexpr int kSeedSides = HOP_SEED_SIDES;  // Morton-neighbour buckets seeded on each side
+#ifndef HOP_LIST_CLASSES
+#define HOP_LIST_CLASSES 7
+#endif
+constexpr int kListClasses = HOP_LIST_CLASSES;  // distance classes of the leaf list
 constexpr int kHeapSlots = 65; // 4-ary heap: slots up to 4*15+4 are read
 
 struct KnnArgs {
@@ -592,10 +596,17 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         hf = h - 1;
     }
     // list of ranges (node | level << 27), leaves already offered removed,
-    // leaves overlapping the bucket box first
+    // ordered by distance class from the bucket box (overlapping, within a
+    // quarter and a half of the largest bound, the rest), so that the heaps
+    // tighten early and later candidates are rejected by the bound
     int lcnt = 0;
     {
-        for (int pass = 0; pass < 2; pass++) {
+        // class thresholds on the squared gap, as fractions of the largest bound
+        double cth[kListClasses];
+#pragma unroll
+        for (int c = 1; c < kListClasses; c++)
+            cth[c] = tmax * __builtin_ldexp(1.0, -2 * (kListClasses - 1 - c));
+        for (int pass = 0; pass < kListClasses; pass++) {
             for (int base = 0; base < fcnt; base += 64) {
                 const int i = base + lane;
                 bool keep = false;
@@ -608,8 +619,11 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
                     const bool done = hf == 0 && first * HOP_LEAF >= seed_lo &&
                                       min(last * HOP_LEAF, a.n) <= seed_hi;
                     const NodeBox nb = a.boxes[a.lv.off[hf] + node];
-                    const bool near = boxbox_d2<PERIODIC>(bb, nb, a.gmask) == 0.0;
-                    keep = !done && (pass == 0 ? near : !near);
+                    const double bd = boxbox_d2<PERIODIC>(bb, nb, a.gmask);
+                    int cls = 0;
+#pragma unroll
+                    for (int c = 1; c < kListClasses; c++) cls += bd > (c == 1 ? 0.0 : cth[c - 1]) ? 1 : 0;
+                    keep = !done && cls == pass;
                 }
                 const uint64_t m = __ballot(keep);
                 const int pos = lcnt + (int)__popcll(m & lt_mask);
@@ -712,7 +726,10 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
             if (bi + 1 < nbatch) nxt_ok = fetch(nxt);
             if (!__any(ok)) continue;
             n_lv += 4;
+            // the query itself never appears here: its own bucket lies in the
+            // seeded range, which the loader skips
             uint64_t pass = 0;
+#pragma unroll
             for (int k0 = 0; k0 < 64; k0 += 16) {
                 SortedRec pr[16];
 #pragma unroll
@@ -723,7 +740,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
                     const double d2 = FAST ? d2_direct(qx, qy, qz, pr[k]) : d2_wrap(qx, qy, qz, pr[k], G);
-                    pass |= (uint64_t)((d2 <= tau && pr[k].tk != mytk) ? 1u : 0u) << (k0 + k);
+                    pass |= (uint64_t)(d2 <= tau ? 1u : 0u) << (k0 + k);
                 }
             }
             insert_marked(pass, PERIODIC && !FAST);
