@@ -44,6 +44,53 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# HBM traffic of the kNN kernel from hardware counters (FETCH_SIZE and
+# WRITE_SIZE, each scaled by what the counter reads for a device copy of
+# known size), kept with a hash of the kernel's sources: the figure is
+# reported only while the sources are the ones it was measured on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "knn_traffic_nfw134m.txt")
+KNN_SOURCES = [os.path.join(ROOT, "paper_1001_3411_amd", "csrc", f)
+               for f in ("hop_knn.hip", "hop_internal.h")]
+
+
+def knn_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KNN_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """Bytes per kNN launch from the counter summary, or None."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_hash") != knn_source_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_probe():
+    """A plain device copy of 1 GiB (read 1 GiB, write 1 GiB), twice: the
+    reference the traffic counters are scaled by."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy probe: 2 x 1 GiB device copies")
+    del src, dst
+
+
 def cpu_baseline(p, budget_frac=4):
     """The CPU oracle on a bounded sample of the same workload: the particles
     of one sub-cube of side 1/budget_frac of the box, as a non-periodic
@@ -68,7 +115,8 @@ def knn_roofline(n, knn_ms, kernel, value):
     achieved = KNN_BYTES_PER_PARTICLE * n / knn_s / 1e9
     return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": None, "kernel_ms": round(knn_ms, 3),
+            "traffic": measured_traffic() if kernel == "k_knn_density" else None,
+            "kernel_ms": round(knn_ms, 3),
             "path_frac": round(PATH_BYTES_PER_PARTICLE * value / 1e9 / HBM_PEAK_GBS, 5)}
 
 
@@ -329,11 +377,15 @@ def main():
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--search", choices=["compare", "plain"], default="compare")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a 1 GiB device copy first (reference for the traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               f"decomposition is described in the design notes but not built.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
     line = bench_batch(args) if args.workload == "batch64" else bench_box(args)
     print(json.dumps(line), flush=True)
 

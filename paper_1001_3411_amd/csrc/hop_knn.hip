@@ -449,20 +449,30 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     uint64_t tau_key = H.r0;
     double tau = active ? fmin(key_d2(tau_key, a.shift), rcap) : -1.0;
     // offer the particles of the staged batch whose bits are set
+    // (the key of the next marked particle is computed before the heap
+    // update of the current one, so that its LDS read and arithmetic overlap
+    // the heap's dependent LDS round trips)
+    auto next_key = [&](uint64_t &pass, bool wrap) -> uint64_t {
+        if (pass == 0) return ~0ull;
+        const int k = __builtin_ctzll(pass);
+        pass &= pass - 1;
+        const SortedRec p = stage[k];
+        const double d2 = wrap ? d2_wrap(qx, qy, qz, p, G) : d2_direct(qx, qy, qz, p);
+        return make_key(d2, (uint32_t)p.tk, a);
+    };
     auto insert_marked = [&](uint64_t pass, bool wrap) {
-        while (__any(pass != 0)) {
-            if (pass != 0) {
-                const int k = __builtin_ctzll(pass);
-                pass &= pass - 1;
-                const SortedRec p = stage[k];
-                const double d2 = wrap ? d2_wrap(qx, qy, qz, p, G) : d2_direct(qx, qy, qz, p);
-                const uint64_t key = make_key(d2, (uint32_t)p.tk, a);
-                if (key < tau_key) {
-                    rh_replace_root(H, heap, lane, hs, key);
-                    tau_key = H.r0;
-                    tau = fmin(key_d2(tau_key, a.shift), rcap);
-                }
+        bool have = pass != 0;
+        uint64_t key = next_key(pass, wrap);
+        while (__any(have)) {
+            const bool have_next = pass != 0;
+            const uint64_t key_next = next_key(pass, wrap);
+            if (have && key < tau_key) {
+                rh_replace_root(H, heap, lane, hs, key);
+                tau_key = H.r0;
+                tau = fmin(key_d2(tau_key, a.shift), rcap);
             }
+            have = have_next;
+            key = key_next;
         }
     };
     // ... and offer the rest of the bucket (hs < 63 only) and kSeedSides
