@@ -113,9 +113,11 @@ def cpu_baseline(p, budget_frac=4):
 def knn_roofline(n, knn_ms, kernel, value):
     knn_s = knn_ms / 1e3
     achieved = KNN_BYTES_PER_PARTICLE * n / knn_s / 1e9
+    # counter-measured bytes per launch hold for the 134M box's kernel only
+    traffic = measured_traffic() if (kernel == "k_knn_density" and n == 134217728) else None
     return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": measured_traffic() if kernel == "k_knn_density" else None,
+            "traffic": traffic, "traffic_gbs": None if traffic is None else round(traffic / knn_s / 1e9, 2),
             "kernel_ms": round(knn_ms, 3),
             "path_frac": round(PATH_BYTES_PER_PARTICLE * value / 1e9 / HBM_PEAK_GBS, 5)}
 
