@@ -341,8 +341,60 @@ __device__ __forceinline__ void lds_sift(uint64_t *heap, int lane, int hs, int i
 
 // Replace the root by x (x below the root) and restore the heap.  Levels 0
 // and 1 are registers (selected without indexing), deeper levels LDS.
+// The same for a full heap of 63 keys (n_dens = 64), whose depth is fixed:
+// level 2 is slots 5..20, level 3 slots 21..62 (children of slots 5..15;
+// slots 63 and 64 hold 0).  Written without loops, so that the two LDS
+// round trips are the only dependent steps.
+__device__ __forceinline__ void rh_replace_root63(RegHeap &H, uint64_t *heap, int lane, uint64_t x)
+{
+    const uint64_t k0 = H.r1[0], k1 = H.r1[1], k2 = H.r1[2], k3 = H.r1[3];
+    const int m01 = k1 > k0 ? 1 : 0;
+    const uint64_t v01 = k1 > k0 ? k1 : k0;
+    const int m23 = k3 > k2 ? 3 : 2;
+    const uint64_t v23 = k3 > k2 ? k3 : k2;
+    const int m = v23 > v01 ? m23 : m01;  // child 1+m
+    const uint64_t v = v23 > v01 ? v23 : v01;
+    if (v <= x) {
+        H.r0 = x;
+        return;
+    }
+    H.r0 = v;
+    // level 2: the children of slot 1+m
+    const int c = 4 * m + 5;
+    const uint64_t w0 = heap[c * 64 + lane], w1 = heap[(c + 1) * 64 + lane];
+    const uint64_t w2 = heap[(c + 2) * 64 + lane], w3 = heap[(c + 3) * 64 + lane];
+    const int n01 = w1 > w0 ? c + 1 : c;
+    const uint64_t u01 = w1 > w0 ? w1 : w0;
+    const int n23 = w3 > w2 ? c + 3 : c + 2;
+    const uint64_t u23 = w3 > w2 ? w3 : w2;
+    const int nm = u23 > u01 ? n23 : n01;
+    const uint64_t u = u23 > u01 ? u23 : u01;
+    const bool down = u > x;
+    // level 3: the children of slot nm (slots up to 64 are inside the heap
+    // area; those of slots 16..20 do not exist)
+    const int d = 4 * min(nm, 15) + 1;
+    const uint64_t z0 = heap[d * 64 + lane], z1 = heap[(d + 1) * 64 + lane];
+    const uint64_t z2 = heap[(d + 2) * 64 + lane], z3 = heap[(d + 3) * 64 + lane];
+    const int y01i = z1 > z0 ? d + 1 : d;
+    const uint64_t y01 = z1 > z0 ? z1 : z0;
+    const int y23i = z3 > z2 ? d + 3 : d + 2;
+    const uint64_t y23 = z3 > z2 ? z3 : z2;
+    const int ym = y23 > y01 ? y23i : y01i;
+    const uint64_t y = (nm <= 15) ? (y23 > y01 ? y23 : y01) : 0ull;
+    const bool deeper = down && y > x;
+    const uint64_t put1 = down ? u : x;  // into register slot 1+m
+#pragma unroll
+    for (int q = 0; q < 4; q++) H.r1[q] = (q == m) ? put1 : H.r1[q];
+    if (down) heap[nm * 64 + lane] = deeper ? y : x;
+    if (deeper) heap[ym * 64 + lane] = x;
+}
+
 __device__ __forceinline__ void rh_replace_root(RegHeap &H, uint64_t *heap, int lane, int hs, uint64_t x)
 {
+    if (hs == kHeapMax) {
+        rh_replace_root63(H, heap, lane, x);
+        return;
+    }
     if (hs <= 1) {
         H.r0 = x;
         return;
@@ -393,7 +445,8 @@ template <bool PERIODIC, bool IDS>
 __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, const int bcount,
                                            const int64_t plo, const int64_t phi,
                                            const double norm, const float norm32, uint64_t *heap,
-                                           SortedRec *stage, uint32_t *leaves, const uint64_t qmask,
+                                           SortedRec *stage, double *stage_pp, uint32_t *leaves,
+                                           const uint64_t qmask,
                                            const int64_t bucket_id)
 {
     // the walk's two frontier buffers live in the heap area until the heap
@@ -415,6 +468,9 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     const double qx = me.x, qy = me.y, qz = me.z;
     const uint32_t ux = (uint32_t)qx, uy = (uint32_t)qy, uz = (uint32_t)qz;
     const int32_t mytk = me.tk;
+    // for the expanded distance test of the streaming pass
+    const double m2x = -2.0 * qx, m2y = -2.0 * qy, m2z = -2.0 * qz;
+    const double qq = __builtin_fma(qx, qx, __builtin_fma(qy, qy, qz * qz));
     // squared search radius of a bounded (learned-radius) search
     double rcap = 1.0e300;
     if (a.cell_r && active) {
@@ -477,7 +533,9 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     };
     // ... and offer the rest of the bucket (hs < 63 only) and kSeedSides
     //    Morton-neighbour buckets on each side (exact minimum image)
-    for (int side = 0; side < 2 * kSeedSides + 1; side++) {
+    // (nearest buckets first: own, -1, +1, -2, +2, ...)
+    for (int si = 0; si < 2 * kSeedSides + 1; si++) {
+        const int side = kSeedSides + ((si & 1) ? -((si + 1) >> 1) : (si >> 1));
         const int64_t nb0 = max(b0 + (side - kSeedSides) * HOP_BUCKET, plo);
         const int64_t nb1 = side == kSeedSides ? b0 + bcount : min(b0 + (side - kSeedSides + 1) * HOP_BUCKET, phi);
         if (nb0 >= nb1) continue;
@@ -731,6 +789,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
             }
             __syncthreads();
             stage[lane] = r;
+            if (FAST) stage_pp[lane] = __builtin_fma(r.x, r.x, __builtin_fma(r.y, r.y, r.z * r.z));
             __syncthreads();
             for (int s = 0; s < 4 && cur_r < lcnt; s++) cursor_step(cur_r, cur_o);
             if (bi + 1 < nbatch) nxt_ok = fetch(nxt);
@@ -739,18 +798,32 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
             // the query itself never appears here: its own bucket lies in the
             // seeded range, which the loader skips
             uint64_t pass = 0;
+            // FAST: d^2 <= tau  <=>  |p|^2 - 2 p.q <= tau - |q|^2, every term
+            // an integer below 2^53, so the three FMAs below are exact
+            const double tq = tau < 0.0 ? -1.0e300 : tau - qq;
 #pragma unroll
             for (int k0 = 0; k0 < 64; k0 += 16) {
                 SortedRec pr[16];
+                double pp[16];
 #pragma unroll
-                for (int k = 0; k < 16; k++) pr[k] = stage[k0 + k];
+                for (int k = 0; k < 16; k++) {
+                    pr[k] = stage[k0 + k];
+                    if (FAST) pp[k] = stage_pp[k0 + k];
+                }
                 // (the bits go straight into the 64-bit mask: collecting them
                 // in a 16-bit word first gave wrong lists in the persistent
                 // batch kernel with this toolchain)
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
-                    const double d2 = FAST ? d2_direct(qx, qy, qz, pr[k]) : d2_wrap(qx, qy, qz, pr[k], G);
-                    pass |= (uint64_t)(d2 <= tau ? 1u : 0u) << (k0 + k);
+                    bool ok_k;
+                    if (FAST) {
+                        const double e = __builtin_fma(m2x, pr[k].x, __builtin_fma(m2y, pr[k].y,
+                                                       __builtin_fma(m2z, pr[k].z, pp[k])));
+                        ok_k = e <= tq;
+                    } else {
+                        ok_k = d2_wrap(qx, qy, qz, pr[k], G) <= tau;
+                    }
+                    pass |= (uint64_t)(ok_k ? 1u : 0u) << (k0 + k);
                 }
             }
             insert_marked(pass, PERIODIC && !FAST);
@@ -905,13 +978,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 {
     __shared__ uint64_t heap[kHeapSlots * 64];
     __shared__ SortedRec stage[64];
+    __shared__ double stage_pp[64];
     __shared__ uint32_t leaves[kLeafList];
     const int64_t bid = blockIdx.x;
     const int64_t bucket = (bid & 7) * a.xcd_chunk + (bid >> 3);
     if (bucket >= a.n_buckets) return;
     const int64_t b0 = bucket * HOP_BUCKET;
     knn_bucket<PERIODIC, IDS>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n, a.norm,
-                              a.norm32, heap, stage, leaves, ~0ull, bucket);
+                              a.norm32, heap, stage, stage_pp, leaves, ~0ull, bucket);
 }
 
 // Fallback of a bounded search: the listed buckets again, without a radius,
@@ -922,11 +996,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 {
     __shared__ uint64_t heap[kHeapSlots * 64];
     __shared__ SortedRec stage[64];
+    __shared__ double stage_pp[64];
     __shared__ uint32_t leaves[kLeafList];
     const int64_t bucket = list[blockIdx.x];
     const int64_t b0 = bucket * HOP_BUCKET;
     knn_bucket<PERIODIC, IDS>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n, a.norm,
-                              a.norm32, heap, stage, leaves, miss[bucket], bucket);
+                              a.norm32, heap, stage, stage_pp, leaves, miss[bucket], bucket);
 }
 
 // buckets with a recorded miss -> list; count the missed lanes
@@ -952,6 +1027,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 {
     __shared__ uint64_t heap[kHeapSlots * 64];
     __shared__ SortedRec stage[64];
+    __shared__ double stage_pp[64];
     __shared__ uint32_t leaves[kLeafList];
     const int lane = threadIdx.x;
     const int nq = b.xcd_queues ? 8 : 1;
@@ -980,7 +1056,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         const int64_t b0 = plo + (item - b.item_off[lo]) * HOP_BUCKET;
         __syncthreads();
         knn_bucket<PERIODIC, false>(a, b0, (int)min((int64_t)HOP_BUCKET, phi - b0), plo, phi,
-                                    b.norm[sv], b.norm32[sv], heap, stage, leaves, ~0ull, 0);
+                                    b.norm[sv], b.norm32[sv], heap, stage, stage_pp, leaves, ~0ull, 0);
         if (lane == 0) atomicAdd(&b.done[sv], 1u);
     }
 }
