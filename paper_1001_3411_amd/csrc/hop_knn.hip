@@ -707,16 +707,6 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         if (s < hs) heap[s * 64 + lane] = park[s - 5];
     for (int s = hs; s < kHeapSlots; s++) heap[s * 64 + lane] = 0;
     __syncthreads();
-    int nleaf_total = 0;
-    for (int i = lane; i < lcnt; i += 64) {
-        const uint32_t e = leaves[i];
-        const int lvl = (int)(e >> 27);
-        const int64_t first = (int64_t)(e & ((1u << 27) - 1)) << lvl;
-        nleaf_total += (int)min((int64_t)1 << lvl, n_leaf_total - first);
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) nleaf_total += __shfl_xor(nleaf_total, d);
-
     // 3. stream the listed leaves, 4 leaves (64 particles) per batch,
     //    loading batch b+1 while batch b is tested.  When every relevant
     //    separation stays under half the box, the loading lane moves each
@@ -735,32 +725,19 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         cz = 0.5 * ((double)bb.lo[2] + (double)bb.hi[2]);
     }
     fastB = __builtin_amdgcn_readfirstlane(fastB ? 1 : 0) != 0;
-    const int nbatch = (nleaf_total + 3) >> 2;
-    auto range_len = [&](int r, int64_t *first) -> int {
-        const uint32_t e = leaves[r];
-        const int lvl = (int)(e >> 27);
-        *first = (int64_t)(e & ((1u << 27) - 1)) << lvl;
-        return (int)min((int64_t)1 << lvl, n_leaf_total - *first);
-    };
-    auto cursor_step = [&](int &r, int &o) {
-        int64_t f;
-        if (++o >= range_len(r, &f)) {
-            r++;
-            o = 0;
-        }
-    };
-    int cur_r = 0, cur_o = 0;  // wave-uniform leaf cursor
-    auto fetch = [&](SortedRec &r) -> bool {
-        int rr = cur_r, oo = cur_o;
-        for (int s = 0; s < (lane >> 4); s++) {
-            if (rr >= lcnt) break;
-            cursor_step(rr, oo);
-        }
-        if (rr >= lcnt) return false;
-        int64_t first;
-        range_len(rr, &first);
-        const int64_t idx = (first + oo) * HOP_LEAF + (lane & 15);
-        if (idx < plo || idx >= phi) return false;          // another problem
+    // every listed entry spans 2^hf leaves (a subtree cut by the end of the
+    // tree yields indices past n, which the loader drops), so slot s of
+    // batch b is leaf position 4b + s of the list
+    const int64_t n_stream = (int64_t)lcnt << hf;
+    const int nbatch = (int)((n_stream + 3) >> 2);
+    const int64_t omask = ((int64_t)1 << hf) - 1;
+    auto fetch = [&](int bi, SortedRec &r) -> bool {
+        const int64_t pos = 4 * (int64_t)bi + (lane >> 4);
+        if (pos >= n_stream) return false;
+        const uint32_t e = leaves[(int)(pos >> hf)];
+        const int64_t leaf = ((int64_t)(e & ((1u << 27) - 1)) << hf) + (pos & omask);
+        const int64_t idx = leaf * HOP_LEAF + (lane & 15);
+        if (idx < plo || idx >= phi) return false;          // another problem, or past n
         if (idx >= seed_lo && idx < seed_hi) return false;  // offered in the seed
         r = a.recs[idx];
         return true;
@@ -770,7 +747,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     auto stream = [&](auto fast_tag) {
         constexpr bool FAST = decltype(fast_tag)::value;
         SortedRec nxt;
-        bool nxt_ok = nbatch > 0 ? fetch(nxt) : false;
+        bool nxt_ok = nbatch > 0 ? fetch(0, nxt) : false;
         for (int bi = 0; bi < nbatch; bi++) {
             SortedRec r = nxt;
             const bool ok = nxt_ok;
@@ -791,8 +768,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
             stage[lane] = r;
             if (FAST) stage_pp[lane] = __builtin_fma(r.x, r.x, __builtin_fma(r.y, r.y, r.z * r.z));
             __syncthreads();
-            for (int s = 0; s < 4 && cur_r < lcnt; s++) cursor_step(cur_r, cur_o);
-            if (bi + 1 < nbatch) nxt_ok = fetch(nxt);
+            if (bi + 1 < nbatch) nxt_ok = fetch(bi + 1, nxt);
             if (!__any(ok)) continue;
             n_lv += 4;
             // the query itself never appears here: its own bucket lies in the
