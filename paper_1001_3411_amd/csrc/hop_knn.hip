@@ -139,6 +139,14 @@ constexpr int kSeedSides = HOP_SEED_SIDES;  // Morton-neighbour buckets seeded o
 #define HOP_LIST_CLASSES 7
 #endif
 constexpr int kListClasses = HOP_LIST_CLASSES;  // distance classes of the leaf list
+#ifndef HOP_NEAR_CLASSES
+#define HOP_NEAR_CLASSES 4
+#endif
+constexpr int kNearClasses = HOP_NEAR_CLASSES;  // classes streamed before the list is pruned again
+#ifndef HOP_PRUNE_EVERY
+#define HOP_PRUNE_EVERY 16
+#endif
+constexpr int kPruneEvery = HOP_PRUNE_EVERY;  // batches between later prunings
 constexpr int kHeapSlots = 65; // 4-ary heap: slots up to 4*15+4 are read
 
 struct KnnArgs {
@@ -668,6 +676,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     // quarter and a half of the largest bound, the rest), so that the heaps
     // tighten early and later candidates are rejected by the bound
     int lcnt = 0;
+    int l_near = 0;  // entries of the near classes
     {
         // class thresholds on the squared gap, as fractions of the largest bound
         double cth[kListClasses];
@@ -698,6 +707,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
                 if (keep) leaves[pos] = e;
                 lcnt += (int)__popcll(m);
             }
+            if (pass == kNearClasses - 1) l_near = lcnt;
         }
     }
     __syncthreads();
@@ -728,8 +738,50 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     // every listed entry spans 2^hf leaves (a subtree cut by the end of the
     // tree yields indices past n, which the loader drops), so slot s of
     // batch b is leaf position 4b + s of the list
-    const int64_t n_stream = (int64_t)lcnt << hf;
-    const int nbatch = (int)((n_stream + 3) >> 2);
+    int64_t n_stream = (int64_t)lcnt << hf;
+    int nbatch = (int)((n_stream + 3) >> 2);
+    // after the near classes, and then every kPruneEvery batches, the
+    // entries not streamed yet are tested again against the groups' bounds
+    // as they are then (the heaps tighten as the stream goes) and the list
+    // is compacted; a cut falls where a batch boundary meets an entry
+    // boundary
+    const int align = hf >= 2 ? 1 : (4 >> hf);
+    const int bi_cut = (int)(((int64_t)(min(lcnt, ((l_near + align - 1) / align) * align)) << hf) >> 2);
+    auto reprune = [&](const int e_cut) {
+        double gt2[8];
+        {
+            double t = tau;
+#pragma unroll
+            for (int d = 1; d < 8; d <<= 1) t = fmax(t, __shfl_xor(t, d));
+#pragma unroll
+            for (int g = 0; g < 8; g++) {
+                const long long tb = __double_as_longlong(t);
+                const int tlo = __builtin_amdgcn_readlane((int)(tb & 0xffffffff), 8 * g);
+                const int thi = __builtin_amdgcn_readlane((int)(tb >> 32), 8 * g);
+                gt2[g] = __longlong_as_double(((long long)thi << 32) | (uint32_t)tlo);
+            }
+        }
+        int nc = e_cut;
+        for (int base = e_cut; base < lcnt; base += 64) {
+            const int i = base + lane;
+            bool keep = false;
+            uint32_t e = 0;
+            if (i < lcnt) {
+                e = leaves[i];
+                const NodeBox nb = a.boxes[a.lv.off[hf] + (e & ((1u << 27) - 1))];
+#pragma unroll
+                for (int g = 0; g < 8; g++) keep |= boxbox_d2<PERIODIC>(gbox[g], nb, a.gmask) <= gt2[g];
+            }
+            const uint64_t m = __ballot(keep);
+            // entries of this chunk are in registers; writes land at or
+            // before the chunk, never on an entry still to be read
+            if (keep) leaves[nc + (int)__popcll(m & lt_mask)] = e;
+            nc += (int)__popcll(m);
+        }
+        lcnt = nc;
+        n_stream = (int64_t)lcnt << hf;
+        nbatch = (int)((n_stream + 3) >> 2);
+    };
     const int64_t omask = ((int64_t)1 << hf) - 1;
     auto fetch = [&](int bi, SortedRec &r) -> bool {
         const int64_t pos = 4 * (int64_t)bi + (lane >> 4);
@@ -748,7 +800,23 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         constexpr bool FAST = decltype(fast_tag)::value;
         SortedRec nxt;
         bool nxt_ok = nbatch > 0 ? fetch(0, nxt) : false;
+        int next_cut = bi_cut;
         for (int bi = 0; bi < nbatch; bi++) {
+            if (bi == next_cut) {
+                const int64_t p0 = 4 * (int64_t)bi;
+                if ((p0 & omask) != 0) {
+                    next_cut = bi + 1;  // not an entry boundary yet
+                } else {
+                    next_cut = bi + kPruneEvery;
+                    if ((int)(p0 >> hf) < lcnt) {
+                        __syncthreads();
+                        reprune((int)(p0 >> hf));
+                        __syncthreads();
+                        if (bi >= nbatch) break;
+                        nxt_ok = fetch(bi, nxt);
+                    }
+                }
+            }
             SortedRec r = nxt;
             const bool ok = nxt_ok;
             if (ok) {
