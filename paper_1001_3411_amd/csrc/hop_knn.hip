@@ -15,17 +15,20 @@
 // (d^2, id) exactly (d^2 is an exact integer held in FP64); the heap's top
 // two levels sit in registers, the rest in LDS.  The search runs in three
 // passes:
-//   1. seed: the bucket's own particles and three Morton-neighbour buckets on
+//   1. seed: the bucket's own particles and one Morton-neighbour bucket on
 //      each side are offered, which gives every lane a finite bound;
 //   2. walk: a breadth-first descent of the tree, 64 child boxes tested per
 //      step against the boxes and bounds of 8 groups of 8 lanes; it stops at
 //      the level where the surviving frontier would exceed the leaf list,
 //      so the list may hold whole subtrees (ranges of leaves) as well as
 //      single leaves;
-//   3. stream: the listed leaves -- first those touching the bucket's own
-//      box -- are loaded 64 particles at a time, each particle tested by all
-//      lanes against their current bounds, and the ones that pass inserted
-//      lane by lane.
+//   3. stream: the listed leaves, in classes of increasing distance from
+//      the bucket's box, are loaded 64 particles at a time; each particle is
+//      tested by all lanes against their current bounds (exactly, in FP64)
+//      and the ones that pass are inserted lane by lane.  After the near
+//      classes, and every 16 batches after that, the entries not streamed
+//      yet are tested again against the groups' tightened bounds and the
+//      list is compacted.
 // Only pruning depends on the bounds; every particle that could belong to
 // a lane's list is offered to it, so the result is the exact kNN.
 //
@@ -132,7 +135,7 @@ __global__ void k_level_boxes(NodeBox *__restrict__ boxes, int64_t child_off, in
 
 constexpr int kHeapMax = 63;   // n_dens - 1 <= 63
 #ifndef HOP_SEED_SIDES
-#define HOP_SEED_SIDES 3
+#define HOP_SEED_SIDES 1
 #endif
 constexpr int kSeedSides = HOP_SEED_SIDES;  // Morton-neighbour buckets seeded on each side
 #ifndef HOP_LIST_CLASSES
@@ -642,17 +645,24 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     __syncthreads();
     while (hf > 0) {
         const int h = hf;
+        // a small frontier descends several levels in one step: its
+        // descendants sl levels down fill the 64 lanes (a descendant's box
+        // lies inside its ancestor's, so skipping the levels between prunes
+        // nothing that the level-by-level walk would keep)
+        int sl = 1;
+        while (sl < 6 && sl < h && (fcnt << (sl + 1)) <= 64) sl++;
+        const int hc = h - sl;
         int ncnt = 0;
-        for (int base = 0; base < fcnt; base += 32) {
-            const int ni = base + (lane >> 1);
+        for (int base = 0; base < fcnt; base += (64 >> sl)) {
+            const int ni = base + (lane >> sl);
             bool need = false;
             uint32_t child = 0;
             if (ni < fcnt) {
-                child = 2 * fc[ni] + (uint32_t)(lane & 1);
-                const int64_t cfirst = (int64_t)child << (h - 1);
-                const int64_t clast = cfirst + ((int64_t)1 << (h - 1)) - 1;
-                if (child < (uint32_t)a.lv.cnt[h - 1] && cfirst <= leaf_hi && clast >= leaf_lo) {
-                    const NodeBox cb = a.boxes[a.lv.off[h - 1] + child];
+                child = (fc[ni] << sl) + (uint32_t)(lane & ((1 << sl) - 1));
+                const int64_t cfirst = (int64_t)child << hc;
+                const int64_t clast = cfirst + ((int64_t)1 << hc) - 1;
+                if (child < (uint32_t)a.lv.cnt[hc] && cfirst <= leaf_hi && clast >= leaf_lo) {
+                    const NodeBox cb = a.boxes[a.lv.off[hc] + child];
 #pragma unroll
                     for (int g = 0; g < 8; g++) need |= boxbox_d2<PERIODIC>(gbox[g], cb, a.gmask) <= gt[g];
                 }
@@ -669,7 +679,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         fc = fn;
         fn = t;
         fcnt = ncnt;
-        hf = h - 1;
+        hf = hc;
     }
     // list of ranges (node | level << 27), leaves already offered removed,
     // ordered by distance class from the bucket box (overlapping, within a
