@@ -150,6 +150,7 @@ constexpr int kNearClasses = HOP_NEAR_CLASSES;  // classes streamed before the l
 #define HOP_PRUNE_EVERY 16
 #endif
 constexpr int kPruneEvery = HOP_PRUNE_EVERY;  // batches between later prunings
+constexpr int kWindow = 32;                    // stream positions per interleave window
 constexpr int kHeapSlots = 65; // 4-ary heap: slots up to 4*15+4 are read
 
 struct KnnArgs {
@@ -354,8 +355,10 @@ __device__ __forceinline__ void lds_sift(uint64_t *heap, int lane, int hs, int i
 // and 1 are registers (selected without indexing), deeper levels LDS.
 // The same for a full heap of 63 keys (n_dens = 64), whose depth is fixed:
 // level 2 is slots 5..20, level 3 slots 21..62 (children of slots 5..15;
-// slots 63 and 64 hold 0).  Written without loops, so that the two LDS
-// round trips are the only dependent steps.
+// slots 63 and 64 hold 0).  Written without branches: x equal to the root
+// leaves the heap as it is, both LDS slots on the path are always read and
+// written (a slot that does not move gets its own key back), so the two LDS
+// round trips are the only dependent steps and no lane masks are juggled.
 __device__ __forceinline__ void rh_replace_root63(RegHeap &H, uint64_t *heap, int lane, uint64_t x)
 {
     const uint64_t k0 = H.r1[0], k1 = H.r1[1], k2 = H.r1[2], k3 = H.r1[3];
@@ -365,11 +368,8 @@ __device__ __forceinline__ void rh_replace_root63(RegHeap &H, uint64_t *heap, in
     const uint64_t v23 = k3 > k2 ? k3 : k2;
     const int m = v23 > v01 ? m23 : m01;  // child 1+m
     const uint64_t v = v23 > v01 ? v23 : v01;
-    if (v <= x) {
-        H.r0 = x;
-        return;
-    }
-    H.r0 = v;
+    const bool up = v > x;
+    H.r0 = up ? v : x;
     // level 2: the children of slot 1+m
     const int c = 4 * m + 5;
     const uint64_t w0 = heap[c * 64 + lane], w1 = heap[(c + 1) * 64 + lane];
@@ -380,7 +380,7 @@ __device__ __forceinline__ void rh_replace_root63(RegHeap &H, uint64_t *heap, in
     const uint64_t u23 = w3 > w2 ? w3 : w2;
     const int nm = u23 > u01 ? n23 : n01;
     const uint64_t u = u23 > u01 ? u23 : u01;
-    const bool down = u > x;
+    const bool down = up && u > x;
     // level 3: the children of slot nm (slots up to 64 are inside the heap
     // area; those of slots 16..20 do not exist)
     const int d = 4 * min(nm, 15) + 1;
@@ -391,13 +391,14 @@ __device__ __forceinline__ void rh_replace_root63(RegHeap &H, uint64_t *heap, in
     const int y23i = z3 > z2 ? d + 3 : d + 2;
     const uint64_t y23 = z3 > z2 ? z3 : z2;
     const int ym = y23 > y01 ? y23i : y01i;
-    const uint64_t y = (nm <= 15) ? (y23 > y01 ? y23 : y01) : 0ull;
+    const uint64_t yraw = y23 > y01 ? y23 : y01;
+    const uint64_t y = (nm <= 15) ? yraw : 0ull;
     const bool deeper = down && y > x;
     const uint64_t put1 = down ? u : x;  // into register slot 1+m
 #pragma unroll
-    for (int q = 0; q < 4; q++) H.r1[q] = (q == m) ? put1 : H.r1[q];
-    if (down) heap[nm * 64 + lane] = deeper ? y : x;
-    if (deeper) heap[ym * 64 + lane] = x;
+    for (int q = 0; q < 4; q++) H.r1[q] = (up && q == m) ? put1 : H.r1[q];
+    heap[nm * 64 + lane] = down ? (deeper ? y : x) : u;
+    heap[ym * 64 + lane] = deeper ? x : yraw;
 }
 
 __device__ __forceinline__ void rh_replace_root(RegHeap &H, uint64_t *heap, int lane, int hs, uint64_t x)
@@ -513,47 +514,60 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
 #pragma unroll
         for (int q = 0; q < 4; q++) H.r1[q] = heap[(q + 1) * 64 + lane];
     }
-    uint64_t tau_key = H.r0;
-    double tau = active ? fmin(key_d2(tau_key, a.shift), rcap) : -1.0;
+    double tau = active ? fmin(key_d2(H.r0, a.shift), rcap) : -1.0;
     // offer the particles of the staged batch whose bits are set
     // (the key of the next marked particle is computed before the heap
     // update of the current one, so that its LDS read and arithmetic overlap
     // the heap's dependent LDS round trips)
     auto next_key = [&](uint64_t &pass, bool wrap) -> uint64_t {
-        if (pass == 0) return ~0ull;
-        const int k = __builtin_ctzll(pass);
+        const bool any = pass != 0;
+        const int k = __builtin_ctzll(pass | (1ull << 63));  // 63 when none is left
         pass &= pass - 1;
         const SortedRec p = stage[k];
         const double d2 = wrap ? d2_wrap(qx, qy, qz, p, G) : d2_direct(qx, qy, qz, p);
-        return make_key(d2, (uint32_t)p.tk, a);
+        const uint64_t key = make_key(d2, (uint32_t)p.tk, a);
+        return any ? key : ~0ull;
     };
     auto insert_marked = [&](uint64_t pass, bool wrap) {
         bool have = pass != 0;
         uint64_t key = next_key(pass, wrap);
-        while (__any(have)) {
-            const bool have_next = pass != 0;
-            const uint64_t key_next = next_key(pass, wrap);
-            if (have && key < tau_key) {
-                rh_replace_root(H, heap, lane, hs, key);
-                tau_key = H.r0;
-                tau = fmin(key_d2(tau_key, a.shift), rcap);
+        if (hs == kHeapMax) {
+            while (__any(have)) {
+                const bool have_next = pass != 0;
+                const uint64_t key_next = next_key(pass, wrap);
+                rh_replace_root63(H, heap, lane, (have && key < H.r0) ? key : H.r0);
+                have = have_next;
+                key = key_next;
             }
-            have = have_next;
-            key = key_next;
+        } else {
+            while (__any(have)) {
+                const bool have_next = pass != 0;
+                const uint64_t key_next = next_key(pass, wrap);
+                if (have && key < H.r0) rh_replace_root(H, heap, lane, hs, key);
+                have = have_next;
+                key = key_next;
+            }
         }
+        if (active) tau = fmin(key_d2(H.r0, a.shift), rcap);
     };
     // ... and offer the rest of the bucket (hs < 63 only) and kSeedSides
-    //    Morton-neighbour buckets on each side (exact minimum image)
-    // (nearest buckets first: own, -1, +1, -2, +2, ...)
+    //    Morton-neighbour buckets on each side (exact minimum image).
+    //    Nearest buckets first; the two buckets at distance d go in two
+    //    batches that each take one half of both (lanes 0-31 from bucket -d,
+    //    lanes 32-63 from bucket +d), so the lanes near either side share
+    //    each batch's insertions
     for (int si = 0; si < 2 * kSeedSides + 1; si++) {
-        const int side = kSeedSides + ((si & 1) ? -((si + 1) >> 1) : (si >> 1));
-        const int64_t nb0 = max(b0 + (side - kSeedSides) * HOP_BUCKET, plo);
-        const int64_t nb1 = side == kSeedSides ? b0 + bcount : min(b0 + (side - kSeedSides + 1) * HOP_BUCKET, phi);
-        if (nb0 >= nb1) continue;
-        const int ncnt = (int)(nb1 - nb0);
-        if (side == kSeedSides && hs >= HOP_BUCKET - 1) continue;
+        if (si == 0 && hs >= HOP_BUCKET - 1) continue;
+        int64_t idx = b0 + lane;
+        if (si > 0) {
+            const int64_t d = (si + 1) >> 1;
+            idx = (lane < 32 ? b0 - d * HOP_BUCKET : b0 + d * HOP_BUCKET) + 32 * ((si - 1) & 1) + (lane & 31);
+        }
+        const bool here = si == 0 ? lane < bcount : (idx >= plo && idx < phi);
+        const uint64_t vm = __ballot(here);
+        if (vm == 0) continue;
         __syncthreads();
-        if (lane < ncnt) stage[lane] = a.recs[nb0 + lane];
+        if (here) stage[lane] = a.recs[idx];
         __syncthreads();
         uint64_t pass = 0;
         for (int k0 = 0; k0 < HOP_BUCKET; k0 += 16) {
@@ -565,8 +579,8 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
                 const int kk = k0 + k;
                 const double d2 = PERIODIC ? d2_wrap(qx, qy, qz, pr[k], G) : d2_direct(qx, qy, qz, pr[k]);
                 // own bucket: only the particles the fill did not take
-                const bool fresh = side != kSeedSides || (kk != lane && kk - (kk > lane ? 1 : 0) >= hs);
-                pass |= (uint64_t)((kk < ncnt && fresh && pr[k].tk != mytk && d2 <= tau) ? 1u : 0u) << kk;
+                const bool fresh = si != 0 || (kk != lane && kk - (kk > lane ? 1 : 0) >= hs);
+                pass |= (uint64_t)((((vm >> kk) & 1) && fresh && pr[k].tk != mytk && d2 <= tau) ? 1u : 0u) << kk;
             }
         }
         insert_marked(pass, PERIODIC);
@@ -753,8 +767,8 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     // after the near classes, and then every kPruneEvery batches, the
     // entries not streamed yet are tested again against the groups' bounds
     // as they are then (the heaps tighten as the stream goes) and the list
-    // is compacted; a cut falls where a batch boundary meets an entry
-    // boundary
+    // is compacted; a cut falls where a batch boundary meets an entry and
+    // an interleave-window boundary
     const int align = hf >= 2 ? 1 : (4 >> hf);
     const int bi_cut = (int)(((int64_t)(min(lcnt, ((l_near + align - 1) / align) * align)) << hf) >> 2);
     auto reprune = [&](const int e_cut) {
@@ -794,8 +808,14 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     };
     const int64_t omask = ((int64_t)1 << hf) - 1;
     auto fetch = [&](int bi, SortedRec &r) -> bool {
-        const int64_t pos = 4 * (int64_t)bi + (lane >> 4);
+        int64_t pos = 4 * (int64_t)bi + (lane >> 4);
         if (pos >= n_stream) return false;
+        // a full window of kWindow positions is streamed transposed (batch r
+        // of the window takes positions r, r + kWindow/4, ...), so the four
+        // leaves of a batch lie apart and favour different lanes: the
+        // insertion loop runs as long as its busiest lane
+        constexpr int64_t wm = kWindow - 1, q = kWindow / 4;
+        if ((pos | wm) < n_stream) pos = (pos & ~wm) | ((pos & 3) * q) | ((pos >> 2) & (q - 1));
         const uint32_t e = leaves[(int)(pos >> hf)];
         const int64_t leaf = ((int64_t)(e & ((1u << 27) - 1)) << hf) + (pos & omask);
         const int64_t idx = leaf * HOP_LEAF + (lane & 15);
@@ -814,8 +834,8 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         for (int bi = 0; bi < nbatch; bi++) {
             if (bi == next_cut) {
                 const int64_t p0 = 4 * (int64_t)bi;
-                if ((p0 & omask) != 0) {
-                    next_cut = bi + 1;  // not an entry boundary yet
+                if ((p0 & (omask | (kWindow - 1))) != 0) {
+                    next_cut = bi + 1;  // not an entry and window boundary yet
                 } else {
                     next_cut = bi + kPruneEvery;
                     if ((int)(p0 >> hf) < lcnt) {
