@@ -707,25 +707,32 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
 #pragma unroll
         for (int c = 1; c < kListClasses; c++)
             cth[c] = tmax * __builtin_ldexp(1.0, -2 * (kListClasses - 1 - c));
-        for (int pass = 0; pass < kListClasses; pass++) {
-            for (int base = 0; base < fcnt; base += 64) {
-                const int i = base + lane;
-                bool keep = false;
-                uint32_t e = 0;
-                if (i < fcnt) {
-                    const uint32_t node = fc[i];
-                    e = node | ((uint32_t)hf << 27);
-                    const int64_t first = (int64_t)node << hf;
-                    const int64_t last = min(first + ((int64_t)1 << hf), n_leaf_total);
-                    const bool done = hf == 0 && first * HOP_LEAF >= seed_lo &&
-                                      min(last * HOP_LEAF, a.n) <= seed_hi;
-                    const NodeBox nb = a.boxes[a.lv.off[hf] + node];
-                    const double bd = boxbox_d2<PERIODIC>(bb, nb, a.gmask);
-                    int cls = 0;
+        // every entry's class once (4 bits per chunk of 64; the frontier
+        // holds at most kLeafList entries), then one gather per class
+        uint64_t cls_pack = 0;
+        for (int base = 0, ci = 0; base < fcnt; base += 64, ci++) {
+            const int i = base + lane;
+            int cls = 15;  // not listed
+            if (i < fcnt) {
+                const uint32_t node = fc[i];
+                const int64_t first = (int64_t)node << hf;
+                const int64_t last = min(first + ((int64_t)1 << hf), n_leaf_total);
+                const bool done = hf == 0 && first * HOP_LEAF >= seed_lo &&
+                                  min(last * HOP_LEAF, a.n) <= seed_hi;
+                const NodeBox nb = a.boxes[a.lv.off[hf] + node];
+                const double bd = boxbox_d2<PERIODIC>(bb, nb, a.gmask);
+                int c0 = 0;
 #pragma unroll
-                    for (int c = 1; c < kListClasses; c++) cls += bd > (c == 1 ? 0.0 : cth[c - 1]) ? 1 : 0;
-                    keep = !done && cls == pass;
-                }
+                for (int c = 1; c < kListClasses; c++) c0 += bd > (c == 1 ? 0.0 : cth[c - 1]) ? 1 : 0;
+                cls = done ? 15 : c0;
+            }
+            cls_pack |= (uint64_t)cls << (4 * ci);
+        }
+        for (int pass = 0; pass < kListClasses; pass++) {
+            for (int base = 0, ci = 0; base < fcnt; base += 64, ci++) {
+                const int i = base + lane;
+                const bool keep = i < fcnt && (int)((cls_pack >> (4 * ci)) & 15) == pass;
+                const uint32_t e = keep ? (fc[i] | ((uint32_t)hf << 27)) : 0u;
                 const uint64_t m = __ballot(keep);
                 const int pos = lcnt + (int)__popcll(m & lt_mask);
                 if (keep) leaves[pos] = e;
