@@ -696,9 +696,10 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         hf = hc;
     }
     // list of ranges (node | level << 27), leaves already offered removed,
-    // ordered by distance class from the bucket box (overlapping, within a
-    // quarter and a half of the largest bound, the rest), so that the heaps
-    // tighten early and later candidates are rejected by the bound
+    // ordered by distance class: the squared gap to the nearest group box,
+    // overlapping first, then in steps of 4 up to the largest bound, so
+    // that the heaps tighten early and later candidates are rejected by the
+    // bound
     int lcnt = 0;
     int l_near = 0;  // entries of the near classes
     {
@@ -720,7 +721,9 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
                 const bool done = hf == 0 && first * HOP_LEAF >= seed_lo &&
                                   min(last * HOP_LEAF, a.n) <= seed_hi;
                 const NodeBox nb = a.boxes[a.lv.off[hf] + node];
-                const double bd = boxbox_d2<PERIODIC>(bb, nb, a.gmask);
+                double bd = boxbox_d2<PERIODIC>(gbox[0], nb, a.gmask);
+#pragma unroll
+                for (int g = 1; g < 8; g++) bd = fmin(bd, boxbox_d2<PERIODIC>(gbox[g], nb, a.gmask));
                 int c0 = 0;
 #pragma unroll
                 for (int c = 1; c < kListClasses; c++) c0 += bd > (c == 1 ? 0.0 : cth[c - 1]) ? 1 : 0;
