@@ -1,7 +1,7 @@
 """Benchmark of the whole HOP hot path on one MI355X.
 
-One step = hop_density (Morton sort, tree, kNN + FP64 density) + hop_link +
-hop_groups + hop_merge over the 134,217,728-particle clustered box (40,000
+One step = hop_density_link (Morton sort, tree, kNN + FP64 density, links
+formed in Morton order) + hop_groups + hop_merge over the 134,217,728-particle clustered box (40,000
 NFW clumps, 30% uniform background), inputs resident in HBM.  Prints one
 JSON line with the roofline of the kNN kernel and the CPU oracle's rate.
 
@@ -34,9 +34,13 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per particle of the kNN + density kernel:
 # read the sorted position (12) and its index (4); write 64 neighbour
-# indices (256) and the density (8)
+# indices (256) and the density (8); in the fused density + link call
+# (the box workload) it also writes the Morton-order copy of the first 16
+# indices and the density (72) that the link kernel reads
 KNN_BYTES_PER_PARTICLE = 12 + 4 + 4 * 64 + 8
-# whole path (all stages), bytes per particle, same accounting
+KNN_COPY_BYTES_PER_PARTICLE = 4 * 16 + 8
+# whole path (all stages), bytes per particle, same accounting; the fused
+# call adds the copy and each particle's index read back by the link (76)
 PATH_BYTES_PER_PARTICLE = 438
 
 
@@ -110,16 +114,19 @@ def cpu_baseline(p, budget_frac=4):
                       f"boundaries, merge, labels), {dt:.1f} s, {r.n_groups} groups"}
 
 
-def knn_roofline(n, knn_ms, kernel, value):
+def knn_roofline(n, knn_ms, kernel, value, fused=False):
     knn_s = knn_ms / 1e3
-    achieved = KNN_BYTES_PER_PARTICLE * n / knn_s / 1e9
+    per = KNN_BYTES_PER_PARTICLE + (KNN_COPY_BYTES_PER_PARTICLE if fused else 0)
+    path = PATH_BYTES_PER_PARTICLE + (KNN_COPY_BYTES_PER_PARTICLE + 4 if fused else 0)
+    achieved = per * n / knn_s / 1e9
     # counter-measured bytes per launch hold for the 134M box's kernel only
     traffic = measured_traffic() if (kernel == "k_knn_density" and n == 134217728) else None
     return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
             "traffic": traffic, "traffic_gbs": None if traffic is None else round(traffic / knn_s / 1e9, 2),
             "kernel_ms": round(knn_ms, 3),
-            "path_frac": round(PATH_BYTES_PER_PARTICLE * value / 1e9 / HBM_PEAK_GBS, 5)}
+            "bytes_per_particle": per,
+            "path_frac": round(path * value / 1e9 / HBM_PEAK_GBS, 5)}
 
 
 def radius_models(ctx, log_fn):
@@ -197,7 +204,7 @@ def bench_box(args):
     groups, chains = out["n_groups"], out["n_chains"]
     log(f"{args.steps} steps: {ms_step:.2f} ms/step, knn {np.mean(knn_ms):.2f} ms, "
         f"sort+tree {np.mean(sort_ms):.2f} ms, groups={groups} chains={chains}")
-    roofline = knn_roofline(n, float(np.mean(knn_ms)), "k_knn_density", value)
+    roofline = knn_roofline(n, float(np.mean(knn_ms)), "k_knn_density", value, fused=True)
     search = None
     if args.search == "compare":
         from dataclasses import replace
@@ -363,7 +370,7 @@ def bench_batch(args):
                        "periodic": False, "padded_rules": True, "groups": groups,
                        "tuning": tune["tuning"]},
             "sequential": {"ms_per_step": ms_seq, "value": n / (dt_seq / args.steps),
-                           "launches": "64 x (hop_density, hop_link, hop_groups, hop_merge)"},
+                           "launches": "64 x (hop_density_link, hop_groups, hop_merge)"},
             "speedup_vs_sequential": ms_seq / ms_step,
             "roofline": knn_roofline(n, float(np.mean(knn_ms)), "k_knn_batch", value),
             "cpu_baseline": cpu}

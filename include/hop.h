@@ -7,6 +7,7 @@
  *
  *   hop_density  kNN (N_dens nearest, self included) + SPH density  (sec. 2, stage 1)
  *   hop_link     link to the densest of the N_hop nearest            (sec. 2, stage 2)
+ *   hop_density_link  the two above in one call (links formed in Morton order)
  *   hop_groups   chains to self-linked peaks, delta_outer cut        (sec. 2, stage 3; merge step 1)
  *   hop_merge    boundary table, proto-halo and sub-peak merge,
  *                group labels                                        (sec. 2, merge steps 2-5;
@@ -156,6 +157,31 @@ int hop_density(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
 int hop_link(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
              const int64_t *id, const uint8_t *padded, const hop_params *p, int32_t *hop,
              void *stream);
+
+/*
+ * hop_density_link -- hop_density followed by hop_link on its outputs, in
+ * one call (section 2, stages 1 and 2).
+ *
+ * Same results as the two calls: density and nbr as hop_density writes
+ * them, hop as hop_link computes it from them.  With n_hop <= 16 the
+ * search also keeps, in the context, a copy of each particle's first 16
+ * list entries and its density at its position in Morton order, and the
+ * links are formed in that order: the neighbours' densities are then
+ * gathered by threads that are neighbours in space, mostly from cache,
+ * instead of at random.  The copy costs 72 bytes per particle of context
+ * memory (held until the context is destroyed).
+ *
+ * pos, id  as for hop_density
+ * padded   [n] uint8 (nonzero = padded) or NULL, as for hop_link
+ * density  [n] output
+ * nbr      [n][k_store] output, or NULL when n_hop <= 16
+ * hop      [n] output
+ * Errors: those of hop_density and hop_link; HOP_ERR_ARG when nbr is NULL
+ * and n_hop > 16.
+ */
+int hop_density_link(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
+                     const uint8_t *padded, const hop_params *p, double *density, int32_t *nbr,
+                     int32_t *hop, void *stream);
 
 /*
  * hop_groups -- chains (section 2, stage 3 and merge step 1).

@@ -110,6 +110,7 @@ def load():
     L.hop_last_error.restype = C.c_char_p
     L.hop_density.argtypes = [vp, i64, vp, vp, C.POINTER(_Params), vp, vp, vp]
     L.hop_link.argtypes = [vp, i64, vp, vp, vp, vp, C.POINTER(_Params), vp, vp]
+    L.hop_density_link.argtypes = [vp, i64, vp, vp, vp, C.POINTER(_Params), vp, vp, vp, vp]
     L.hop_groups.argtypes = [vp, i64, vp, vp, vp, C.POINTER(_Params), vp, vp,
                              C.POINTER(i32), vp]
     L.hop_merge.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, C.POINTER(_Params), vp,
@@ -208,6 +209,25 @@ class HopContext:
                                          _ptr(nbr), self._stream(stream)))
         return dens, nbr
 
+    def density_link(self, pos, params: HopParams | None = None, ids=None, padded=None,
+                     want_nbr=True, stream=None):
+        """hop_density_link: (density, nbr or None, hop) in one call."""
+        torch = self._torch
+        p = params or HopParams()
+        pos = self._dev(pos, torch.int32).view(torch.int32)
+        n = pos.shape[0]
+        dens = torch.empty(n, dtype=torch.float64, device=pos.device)
+        nbr = torch.empty((n, p.k_store), dtype=torch.int32, device=pos.device) if want_nbr else None
+        hop = torch.empty(n, dtype=torch.int32, device=pos.device)
+        cp = p.c()
+        # converted inputs stay referenced until the call has enqueued its
+        # work: a temporary freed earlier could be handed to the next one
+        ids_d, pad_d = self._dev(ids, torch.int64), self._dev(padded, torch.uint8)
+        self._check(self.lib.hop_density_link(self.h, n, _ptr(pos), _ptr(ids_d), _ptr(pad_d),
+                                              C.byref(cp), _ptr(dens), _ptr(nbr), _ptr(hop),
+                                              self._stream(stream)))
+        return dens, nbr, hop
+
     def link(self, nbr, dens, params: HopParams | None = None, ids=None, padded=None,
              stream=None):
         torch = self._torch
@@ -215,10 +235,9 @@ class HopContext:
         n = nbr.shape[0]
         hop = torch.empty(n, dtype=torch.int32, device=nbr.device)
         cp = p.c()
-        self._check(self.lib.hop_link(self.h, n, _ptr(nbr), _ptr(dens),
-                                      _ptr(self._dev(ids, torch.int64)),
-                                      _ptr(self._dev(padded, torch.uint8)), C.byref(cp),
-                                      _ptr(hop), self._stream(stream)))
+        ids_d, pad_d = self._dev(ids, torch.int64), self._dev(padded, torch.uint8)
+        self._check(self.lib.hop_link(self.h, n, _ptr(nbr), _ptr(dens), _ptr(ids_d), _ptr(pad_d),
+                                      C.byref(cp), _ptr(hop), self._stream(stream)))
         return hop
 
     def groups(self, hop, dens, params: HopParams | None = None, ids=None, stream=None):
@@ -229,8 +248,8 @@ class HopContext:
         chain_of = torch.empty(n, dtype=torch.int32, device=hop.device)
         nc = C.c_int32(0)
         cp = p.c()
-        self._check(self.lib.hop_groups(self.h, n, _ptr(hop), _ptr(dens),
-                                        _ptr(self._dev(ids, torch.int64)), C.byref(cp),
+        ids_d = self._dev(ids, torch.int64)
+        self._check(self.lib.hop_groups(self.h, n, _ptr(hop), _ptr(dens), _ptr(ids_d), C.byref(cp),
                                         _ptr(root), _ptr(chain_of), C.byref(nc),
                                         self._stream(stream)))
         return root, chain_of, int(nc.value)
@@ -246,11 +265,10 @@ class HopContext:
             table = torch.empty((max(n_chains, 1), 3), dtype=torch.int64, device=nbr.device)
         ng = C.c_int32(0)
         cp = p.c()
+        ids_d, pad_d = self._dev(ids, torch.int64), self._dev(padded, torch.uint8)
         self._check(self.lib.hop_merge(self.h, n, _ptr(nbr), _ptr(dens), _ptr(root),
-                                       _ptr(chain_of), n_chains,
-                                       _ptr(self._dev(ids, torch.int64)),
-                                       _ptr(self._dev(padded, torch.uint8)), C.byref(cp),
-                                       _ptr(group), C.byref(ng), _ptr(table),
+                                       _ptr(chain_of), n_chains, _ptr(ids_d), _ptr(pad_d),
+                                       C.byref(cp), _ptr(group), C.byref(ng), _ptr(table),
                                        self._stream(stream)))
         g = int(ng.value)
         out = {"group": group, "n_groups": g}
@@ -264,11 +282,16 @@ class HopContext:
     def sync(self, stream=None):
         self._check(self.lib.hop_sync(self.h, self._stream(stream)))
 
-    def run(self, pos, params: HopParams | None = None, ids=None, padded=None, stream=None):
-        """All four stages; returns a dict of device tensors."""
+    def run(self, pos, params: HopParams | None = None, ids=None, padded=None, stream=None,
+            fused=True):
+        """All four stages; returns a dict of device tensors.  fused: density
+        and links in one hop_density_link call (else hop_density, hop_link)."""
         p = params or HopParams()
-        dens, nbr = self.density(pos, p, ids=ids, stream=stream)
-        hop = self.link(nbr, dens, p, ids=ids, padded=padded, stream=stream)
+        if fused:
+            dens, nbr, hop = self.density_link(pos, p, ids=ids, padded=padded, stream=stream)
+        else:
+            dens, nbr = self.density(pos, p, ids=ids, stream=stream)
+            hop = self.link(nbr, dens, p, ids=ids, padded=padded, stream=stream)
         root, chain_of, nc = self.groups(hop, dens, p, ids=ids, stream=stream)
         out = self.merge(nbr, dens, root, chain_of, nc, p, ids=ids, padded=padded,
                          stream=stream)

@@ -157,7 +157,8 @@ void hop_ctx_destroy(hop_ctx *ctx)
                       &ctx->work_a, &ctx->work_b, &ctx->work_c, &ctx->work_d, &ctx->work_e,
                       &ctx->work_f, &ctx->hash_keys, &ctx->hash_vals, &ctx->edges_lo,
                       &ctx->edges_hi, &ctx->edges_s, &ctx->batch_tab, &ctx->batch_aux,
-                      &ctx->cell_counts, &ctx->cell_r, &ctx->radius_w, &ctx->mlp_part, &ctx->miss};
+                      &ctx->cell_counts, &ctx->cell_r, &ctx->radius_w, &ctx->mlp_part, &ctx->miss,
+                      &ctx->srt_nbr, &ctx->srt_dens};
     for (DevBuf *b : bufs)
         if (b->ptr) hipFree(b->ptr);
     if (ctx->hflags) hipHostFree(ctx->hflags);
@@ -220,7 +221,34 @@ int hop_density(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
     HOPTRY(hop_check_params(ctx, n, p));
     if (!pos || !density) return hop_fail(ctx, HOP_ERR_ARG, "pos and density must be non-NULL");
     HOPTRY(hop_set_device(ctx));
-    return hop_density_impl(ctx, n, pos, id, p, density, nbr, (hipStream_t)stream);
+    return hop_density_impl(ctx, n, pos, id, p, density, nbr, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int hop_density_link(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
+                     const uint8_t *padded, const hop_params *p, double *density, int32_t *nbr,
+                     int32_t *hop, void *stream)
+{
+    if (!ctx) return HOP_ERR_ARG;
+    ctx->err.clear();
+    HOPTRY(hop_check_params(ctx, n, p));
+    if (!pos || !density || !hop) return hop_fail(ctx, HOP_ERR_ARG, "pos, density and hop must be non-NULL");
+    HOPTRY(hop_set_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    if (p->n_hop > 16) {
+        // no sorted copy for longer link lists: the two calls as they are
+        if (!nbr) return hop_fail(ctx, HOP_ERR_ARG, "nbr must be non-NULL when n_hop > 16");
+        HOPTRY(hop_density_impl(ctx, n, pos, id, p, density, nbr, nullptr, nullptr, s));
+        const int32_t *tk = id ? (const int32_t *)ctx->tk.ptr : nullptr;
+        return hop_link_impl(ctx, n, nbr, density, tk, padded, p, hop, s);
+    }
+    const size_t rows = (size_t)hop_div_up(n, HOP_BUCKET) * HOP_BUCKET;
+    HOPTRY(hop_reserve(ctx, ctx->srt_nbr, rows * 16 * 4));
+    HOPTRY(hop_reserve(ctx, ctx->srt_dens, rows * 8));
+    int32_t *nbr16s = (int32_t *)ctx->srt_nbr.ptr;
+    double *dens_s = (double *)ctx->srt_dens.ptr;
+    HOPTRY(hop_density_impl(ctx, n, pos, id, p, density, nbr, nbr16s, dens_s, s));
+    const int32_t *tk = id ? (const int32_t *)ctx->tk.ptr : nullptr;
+    return hop_link_sorted_impl(ctx, n, nbr16s, dens_s, density, tk, padded, p, hop, s);
 }
 
 int hop_link(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,

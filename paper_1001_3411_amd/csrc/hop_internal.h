@@ -74,6 +74,7 @@ struct hop_ctx {
     DevBuf cell_counts, cell_r;   // learned radius: particles and search radius per cell
     DevBuf radius_w, mlp_part;    // BF16 model weights; training partial sums
     DevBuf miss;                  // learned radius: per-bucket lanes to search again
+    DevBuf srt_nbr, srt_dens;     // density + links: sorted copies of list heads and densities
     int radius_kind = 0;          // HOP_RADIUS_* of the loaded model, 0 = none
     float radius_margin = 0.0f;
     float radius_occupancy = 8.0f;
@@ -128,11 +129,21 @@ int hop_radix_sort(hop_ctx *ctx, uint64_t *keys, uint32_t *vals, uint64_t *tk, u
 // Builds the tie keys for ids (tk[i] = rank of (id_i, i)) into ctx->tk and
 // the inverse into ctx->tk2j.
 int hop_build_tiekeys(hop_ctx *ctx, int64_t n, const int64_t *id, hipStream_t s);
+// nbr16s / dens_s (both NULL or both set, n rounded up to whole buckets):
+// a copy of the first 16 list entries and of the densities in Morton
+// (sorted) order, for hop_link_sorted_impl.
 int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
-                     const hop_params *p, double *density, int32_t *nbr, hipStream_t s);
+                     const hop_params *p, double *density, int32_t *nbr, int32_t *nbr16s,
+                     double *dens_s, hipStream_t s);
 int hop_link_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
                   const int32_t *tk, const uint8_t *padded, const hop_params *p, int32_t *hop,
                   hipStream_t s);
+// The same links from the sorted copies of the last hop_density_impl on
+// this context (its ctx->recs gives each sorted position's particle);
+// needs n_hop <= 16.
+int hop_link_sorted_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr16s, const double *dens_s,
+                         const double *density, const int32_t *tk, const uint8_t *padded,
+                         const hop_params *p, int32_t *hop, hipStream_t s);
 // Leaves the exclusive scan of the chain-root flags (indexed by tie key)
 // in ctx->work_a: entry k = number of chains whose root has tie key < k.
 int hop_groups_impl(hop_ctx *ctx, int64_t n, const int32_t *hop, const double *density,

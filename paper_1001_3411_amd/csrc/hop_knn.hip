@@ -175,6 +175,10 @@ struct KnnArgs {
     float norm32;        // norm rounded to FP32
     int32_t *nbr;
     double *dens;
+    // (NULL = off) the first 16 list entries and the density again, at the
+    // query's sorted position: rows of 64 B written by consecutive lanes
+    int32_t *nbr16s;
+    double *dens_s;
     const int32_t *tk2j;
     uint32_t *dflags;
     unsigned long long *counters;  // [0] nodes tested, [1] leaves scanned (NULL = off)
@@ -1029,15 +1033,22 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
 
     const int32_t jq = me.j;
     a.dens[jq] = delta;
+    auto col = [&](int t) -> int32_t {
+        if (t == 0) return jq;
+        const uint32_t tkv = (uint32_t)(v[t - 1] & a.tk_mask);
+        // an unfilled slot (flagged above) must not index the table
+        if (IDS) return tkv < (uint64_t)a.n ? a.tk2j[tkv] : -1;
+        return (int32_t)tkv;
+    };
+    if (a.nbr16s) {
+        int4 *dst = reinterpret_cast<int4 *>(a.nbr16s + (b0 + lane) * 16);
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            dst[q] = make_int4(col(4 * q), col(4 * q + 1), col(4 * q + 2), col(4 * q + 3));
+        a.dens_s[b0 + lane] = delta;
+    }
     if (a.nbr) {
         int32_t *row = a.nbr + (int64_t)jq * a.k_store;
-        auto col = [&](int t) -> int32_t {
-            if (t == 0) return jq;
-            const uint32_t tkv = (uint32_t)(v[t - 1] & a.tk_mask);
-            // an unfilled slot (flagged above) must not index the table
-            if (IDS) return tkv < (uint64_t)a.n ? a.tk2j[tkv] : -1;
-            return (int32_t)tkv;
-        };
         if (a.vec_store) {
 #pragma unroll
             for (int t = 0; t < 64; t += 4) {
@@ -1315,7 +1326,8 @@ int start_counters(hop_ctx *ctx, KnnArgs &a, hipStream_t s)
 }  // namespace
 
 int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
-                     const hop_params *p, double *density, int32_t *nbr, hipStream_t s)
+                     const hop_params *p, double *density, int32_t *nbr, int32_t *nbr16s,
+                     double *dens_s, hipStream_t s)
 {
     const uint32_t glim = 1u << p->grid_bits;
     const bool periodic = (p->flags & HOP_PERIODIC) != 0;
@@ -1357,6 +1369,8 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     // 3. kNN + density (bounded by the per-cell search radius if asked for)
     KnnArgs a;
     base_args(ctx, a, n, p, recs, boxes, lv, density, nbr, tk2j);
+    a.nbr16s = nbr16s;
+    a.dens_s = dens_s;
     a.norm = norm_of(p, p->mean_density, n);
     a.norm32 = (float)a.norm;
     const bool learned = (p->flags & HOP_LEARNED_RADIUS) != 0;

@@ -66,6 +66,60 @@ __global__ void k_hop(int64_t n, const int32_t *__restrict__ nbr, int k_store, i
     hop[i] = best;
 }
 
+// The same links in Morton order: thread t takes the particle at sorted
+// position t, its first 16 list entries from the sorted copy (one 64-byte
+// row, consecutive threads on consecutive rows) and its density from the
+// sorted copy; the neighbours' densities are gathered from the input-order
+// array, where the 64 threads of a wave, being neighbours in space, mostly
+// gather the same entries.  Same comparisons in the same order as k_hop.
+__global__ void k_hop_sorted(int64_t n, const SortedRec *__restrict__ recs,
+                             const int32_t *__restrict__ nbr16s, int n_hop,
+                             const double *__restrict__ dens_s, const double *__restrict__ dens,
+                             const int32_t *__restrict__ tk, const uint8_t *__restrict__ padded,
+                             int padded_rules, int32_t *__restrict__ hop,
+                             uint32_t *__restrict__ dflags)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int32_t i = recs[t].j;
+    if (padded_rules && padded && padded[i]) {
+        hop[i] = i;
+        return;
+    }
+    int32_t best = i;
+    double bd = dens_s[t];
+    int32_t bt = tk ? tk[i] : i;
+    const int4 *row = reinterpret_cast<const int4 *>(nbr16s + t * 16);
+    int32_t js[16];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int4 v = row[q];
+        js[4 * q] = v.x;
+        js[4 * q + 1] = v.y;
+        js[4 * q + 2] = v.z;
+        js[4 * q + 3] = v.w;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+        if (s >= n_hop) break;
+        const int32_t j = js[s];
+        if (j < 0 || j >= n) {
+            bad = true;
+            continue;
+        }
+        const double dj = dens[j];
+        const int32_t tj = tk ? tk[j] : j;
+        if (dj > bd || (dj == bd && tj < bt)) {
+            best = j;
+            bd = dj;
+            bt = tj;
+        }
+    }
+    if (bad) atomicOr(dflags, DERR_INDEX);
+    hop[i] = best;
+}
+
 __global__ void k_root_init(int64_t n, const int32_t *__restrict__ hop, int32_t *__restrict__ root,
                             uint32_t *__restrict__ dflags)
 {
@@ -148,6 +202,19 @@ int hop_link_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *den
     k_hop<<<hop_grid(n, 256), 256, 0, s>>>(n, nbr, p->k_store, p->n_hop, density, tk, padded,
                                            (p->flags & HOP_PADDED_RULES) ? 1 : 0, hop,
                                            (uint32_t *)ctx->flags.ptr);
+    HOPCHK(ctx, hipGetLastError());
+    return HOP_OK;
+}
+
+int hop_link_sorted_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr16s, const double *dens_s,
+                         const double *density, const int32_t *tk, const uint8_t *padded,
+                         const hop_params *p, int32_t *hop, hipStream_t s)
+{
+    if (p->n_hop > 16) return hop_fail(ctx, HOP_ERR_ARG, "the sorted link path needs n_hop <= 16");
+    k_hop_sorted<<<hop_grid(n, 256), 256, 0, s>>>(n, (const SortedRec *)ctx->recs.ptr, nbr16s, p->n_hop,
+                                                  dens_s, density, tk, padded,
+                                                  (p->flags & HOP_PADDED_RULES) ? 1 : 0, hop,
+                                                  (uint32_t *)ctx->flags.ptr);
     HOPCHK(ctx, hipGetLastError());
     return HOP_OK;
 }

@@ -41,6 +41,8 @@ def test_null_context_is_rejected_without_device():
     lib.hop_params_default(ctypes.byref(p))
     assert lib.hop_density(None, 100, None, None, ctypes.byref(p), None, None, None) == -1
     assert lib.hop_link(None, 100, None, None, None, None, ctypes.byref(p), None, None) == -1
+    assert lib.hop_density_link(None, 100, None, None, None, ctypes.byref(p), None, None, None,
+                                None) == -1
     assert lib.hop_last_error(None) == b"no context"
 
 
