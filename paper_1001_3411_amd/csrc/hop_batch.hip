@@ -118,12 +118,24 @@ extern "C" int hop_run_batch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets
     HOPTRY(hop_set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
 
-    // 1. kNN + density, one persistent launch
+    // 1. kNN + density, one persistent launch (with the Morton-order copy of
+    //    list heads and densities that the links read, when n_hop <= 16)
     int64_t *sub_off = nullptr;
-    HOPTRY(hop_density_batch_impl(ctx, n_sub, offsets, pos, mean_density, p, density, nbr, &sub_off, s));
+    int32_t *nbr16s = nullptr;
+    double *dens_s = nullptr;
+    if (p->n_hop <= 16) {
+        const size_t rows = (size_t)hop_div_up(n, HOP_BUCKET) * HOP_BUCKET;
+        HOPTRY(hop_reserve(ctx, ctx->srt_nbr, rows * 16 * 4));
+        HOPTRY(hop_reserve(ctx, ctx->srt_dens, rows * 8));
+        nbr16s = (int32_t *)ctx->srt_nbr.ptr;
+        dens_s = (double *)ctx->srt_dens.ptr;
+    }
+    HOPTRY(hop_density_batch_impl(ctx, n_sub, offsets, pos, mean_density, p, density, nbr, nbr16s,
+                                  dens_s, &sub_off, s));
 
     // 2.-3. links and chains on batch-wide indices
-    HOPTRY(hop_link_impl(ctx, n, nbr, density, nullptr, padded, p, hop, s));
+    if (nbr16s) HOPTRY(hop_link_sorted_impl(ctx, n, nbr16s, dens_s, density, nullptr, padded, p, hop, s));
+    else HOPTRY(hop_link_impl(ctx, n, nbr, density, nullptr, padded, p, hop, s));
     int32_t nc = 0;
     HOPTRY(hop_groups_impl(ctx, n, hop, density, nullptr, p, root, chain_of, &nc, s));
     HOPTRY(hop_reserve(ctx, ctx->batch_aux, (size_t)(3 * n_sub + 3) * 4));

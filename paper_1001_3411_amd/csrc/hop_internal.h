@@ -163,7 +163,8 @@ int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *de
 // of the offsets, valid until the next batched call.
 int hop_density_batch_impl(hop_ctx *ctx, int32_t n_sub, const int64_t *off, const uint32_t *pos,
                            const double *mean_density, const hop_params *p, double *density,
-                           int32_t *nbr, int64_t **sub_off_dev, hipStream_t s);
+                           int32_t *nbr, int32_t *nbr16s, double *dens_s, int64_t **sub_off_dev,
+                           hipStream_t s);
 
 // Learned radius: cell side bits for n particles, and the per-cell search
 // radii of pos (cell counts, then the loaded model per cell).

@@ -1426,7 +1426,8 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
 
 int hop_density_batch_impl(hop_ctx *ctx, int32_t n_sub, const int64_t *off, const uint32_t *pos,
                            const double *mean_density, const hop_params *p, double *density,
-                           int32_t *nbr, int64_t **sub_off_dev, hipStream_t s)
+                           int32_t *nbr, int32_t *nbr16s, double *dens_s, int64_t **sub_off_dev,
+                           hipStream_t s)
 {
     const uint32_t glim = 1u << p->grid_bits;
     const bool periodic = (p->flags & HOP_PERIODIC) != 0;
@@ -1499,6 +1500,8 @@ int hop_density_batch_impl(hop_ctx *ctx, int32_t n_sub, const int64_t *off, cons
     // 3. persistent kNN + density over all buckets of all subvolumes
     KnnArgs a;
     base_args(ctx, a, n, p, recs, boxes, lv, density, nbr, nullptr);
+    a.nbr16s = nbr16s;
+    a.dens_s = dens_s;
     HOPTRY(start_counters(ctx, a, s));
     BatchArgs b{};
     b.sub_off = sub_off;
