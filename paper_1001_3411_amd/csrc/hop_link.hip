@@ -3,6 +3,9 @@
 //
 // Links: one lane per particle reads its first n_hop neighbours and their
 // densities; the densest wins, equal densities go to the smaller tie key.
+// k_hop takes particles in input order (any neighbour lists); k_hop_sorted
+// takes them in Morton order from the copy the kNN kernel writes for the
+// fused density + link call, so that a wave's gathers fall in cache.
 // Chains: pointer jumping (root <- root[root]) until no root changes; every
 // step at least halves the remaining distance to the self-linked particle,
 // so a chain of depth D resolves in ceil(log2 D) rounds.  Chains are then
