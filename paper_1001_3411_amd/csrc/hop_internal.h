@@ -139,8 +139,8 @@ int hop_link_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *den
                   const int32_t *tk, const uint8_t *padded, const hop_params *p, int32_t *hop,
                   hipStream_t s);
 // The same links from the sorted copies of the last hop_density_impl on
-// this context (its ctx->recs gives each sorted position's particle);
-// needs n_hop <= 16.
+// this context (entry 0 of each copied row is the particle itself); needs
+// n_hop <= 16.
 int hop_link_sorted_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr16s, const double *dens_s,
                          const double *density, const int32_t *tk, const uint8_t *padded,
                          const hop_params *p, int32_t *hop, hipStream_t s);

@@ -71,12 +71,11 @@ __global__ void k_hop(int64_t n, const int32_t *__restrict__ nbr, int k_store, i
 
 // The same links in Morton order: thread t takes the particle at sorted
 // position t, its first 16 list entries from the sorted copy (one 64-byte
-// row, consecutive threads on consecutive rows) and its density from the
-// sorted copy; the neighbours' densities are gathered from the input-order
+// row, consecutive threads on consecutive rows; entry 0 is the particle
+// itself) and its density from the sorted copy; the neighbours' densities are gathered from the input-order
 // array, where the 64 threads of a wave, being neighbours in space, mostly
 // gather the same entries.  Same comparisons in the same order as k_hop.
-__global__ void k_hop_sorted(int64_t n, const SortedRec *__restrict__ recs,
-                             const int32_t *__restrict__ nbr16s, int n_hop,
+__global__ void k_hop_sorted(int64_t n, const int32_t *__restrict__ nbr16s, int n_hop,
                              const double *__restrict__ dens_s, const double *__restrict__ dens,
                              const int32_t *__restrict__ tk, const uint8_t *__restrict__ padded,
                              int padded_rules, int32_t *__restrict__ hop,
@@ -84,14 +83,6 @@ __global__ void k_hop_sorted(int64_t n, const SortedRec *__restrict__ recs,
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    const int32_t i = recs[t].j;
-    if (padded_rules && padded && padded[i]) {
-        hop[i] = i;
-        return;
-    }
-    int32_t best = i;
-    double bd = dens_s[t];
-    int32_t bt = tk ? tk[i] : i;
     const int4 *row = reinterpret_cast<const int4 *>(nbr16s + t * 16);
     int32_t js[16];
 #pragma unroll
@@ -102,6 +93,18 @@ __global__ void k_hop_sorted(int64_t n, const SortedRec *__restrict__ recs,
         js[4 * q + 2] = v.z;
         js[4 * q + 3] = v.w;
     }
+    const int32_t i = js[0];  // every list starts with the particle itself
+    if (i < 0 || i >= n) {
+        atomicOr(dflags, DERR_INDEX);
+        return;
+    }
+    if (padded_rules && padded && padded[i]) {
+        hop[i] = i;
+        return;
+    }
+    int32_t best = i;
+    double bd = dens_s[t];
+    int32_t bt = tk ? tk[i] : i;
     bool bad = false;
 #pragma unroll
     for (int s = 0; s < 16; s++) {
@@ -214,7 +217,7 @@ int hop_link_sorted_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr16s, const d
                          const hop_params *p, int32_t *hop, hipStream_t s)
 {
     if (p->n_hop > 16) return hop_fail(ctx, HOP_ERR_ARG, "the sorted link path needs n_hop <= 16");
-    k_hop_sorted<<<hop_grid(n, 256), 256, 0, s>>>(n, (const SortedRec *)ctx->recs.ptr, nbr16s, p->n_hop,
+    k_hop_sorted<<<hop_grid(n, 256), 256, 0, s>>>(n, nbr16s, p->n_hop,
                                                   dens_s, density, tk, padded,
                                                   (p->flags & HOP_PADDED_RULES) ? 1 : 0, hop,
                                                   (uint32_t *)ctx->flags.ptr);
