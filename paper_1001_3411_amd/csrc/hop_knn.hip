@@ -639,8 +639,8 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
 
     // 2. breadth-first walk: keep the nodes within a group's bound of that
     //    group's box; 64 lanes test 64 children at once.  The frontier uses
-    //    the heap's LDS levels, so levels 2-3 of the heap are parked in the
-    //    leaf list meanwhile.
+    //    the heap's LDS levels, so levels 2-3 of the heap are parked in
+    //    registers meanwhile.
     NodeBox bb;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
