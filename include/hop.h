@@ -12,6 +12,8 @@
  *   hop_merge    boundary table, proto-halo and sub-peak merge,
  *                group labels                                        (sec. 2, merge steps 2-5;
  *                                                                     sec. 3.1 last step)
+ *   hop_halo_stats  per-halo count, centre, maximum radius, bulk velocity
+ *                (sec. 3.1 output step)
  *
  * Conventions shared by every entry point
  * ----------------------------------------
@@ -232,6 +234,37 @@ int hop_merge(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density
               const int32_t *root, const int32_t *chain_of, int32_t n_chains, const int64_t *id,
               const uint8_t *padded, const hop_params *p, int32_t *group, int32_t *n_groups,
               hop_group_info *groups, void *stream);
+
+/*
+ * hop_halo_stats -- per-halo statistics (section 3.1, the output step: each
+ * task reports its halos' particle count, centre of mass, maximum radius
+ * and bulk velocity; the paper gives no formulas, this is the reading).
+ *
+ * Members of halo g are the particles with group[i] == g.  Offsets are the
+ * integer displacements from the halo's peak particle (groups[g].peak),
+ * taken as the minimum image in [-G/2, G/2) under HOP_PERIODIC (G =
+ * 2^grid_bits), plain differences otherwise.  With m = (sum of offsets) /
+ * count (exact integer sum, one FP64 division):
+ *   com[g]   = peak position + m, wrapped into [0, G) under HOP_PERIODIC;
+ *   rmax[g]  = max over members of sqrt((dx-mx)^2 + (dy-my)^2 + (dz-mz)^2),
+ *              FP64, x + y summed first, correctly rounded square root;
+ *   vbulk[g] = mean member velocity, FP64 sum (atomic: the summation order,
+ *              and so the last bits, vary within the FP64 summation bound).
+ * com and rmax are exact functions of the inputs (the same in every run).
+ *
+ * pos      [n][3] uint32 as given to hop_density
+ * vel      [n][3] float or NULL (then vbulk is not written)
+ * group    [n] from hop_merge (-1 = no halo)
+ * groups   [n_groups] the table from hop_merge (count and peak are read)
+ * com      [n_groups][3] FP64 output
+ * rmax     [n_groups] FP64 output
+ * vbulk    [n_groups][3] FP64 output, or NULL when vel is NULL
+ * Errors: HOP_ERR_ARG for bad sizes or NULL outputs; a group number or
+ * peak outside range is reported by the next synchronising call.
+ */
+int hop_halo_stats(hop_ctx *ctx, int64_t n, const uint32_t *pos, const float *vel,
+                   const int32_t *group, int32_t n_groups, const hop_group_info *groups,
+                   const hop_params *p, double *com, double *rmax, double *vbulk, void *stream);
 
 /*
  * hop_run_batch -- the whole path (density, links, chains, merge, labels)

@@ -115,6 +115,7 @@ def load():
                              C.POINTER(i32), vp]
     L.hop_merge.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, C.POINTER(_Params), vp,
                             C.POINTER(i32), vp, vp]
+    L.hop_halo_stats.argtypes = [vp, i64, vp, vp, vp, i32, vp, C.POINTER(_Params), vp, vp, vp, vp]
     L.hop_run_batch.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(_Params), vp, vp, vp, vp, vp,
                                 vp, vp, vp, vp, vp, vp]
     f32 = C.c_float
@@ -274,9 +275,33 @@ class HopContext:
         out = {"group": group, "n_groups": g}
         if want_table:
             t = table[:g]
+            out["table"] = t
             out["g_count"] = t[:, 0].clone()
             out["g_peak"] = (t[:, 1] & 0xFFFFFFFF).to(torch.int32)
             out["g_peak_dens"] = t[:, 2].contiguous().view(torch.float64)
+        return out
+
+    def halo_stats(self, pos, group, table, params: HopParams | None = None, vel=None,
+                   stream=None):
+        """hop_halo_stats: per-halo centre of mass, maximum radius and (with
+        vel) bulk velocity; table is merge()["table"]."""
+        torch = self._torch
+        p = params or HopParams()
+        pos_d = self._dev(pos, torch.int32).view(torch.int32)
+        vel_d = self._dev(vel, torch.float32)
+        n = pos_d.shape[0]
+        ng = table.shape[0]
+        dev = pos_d.device
+        com = torch.empty((max(ng, 1), 3), dtype=torch.float64, device=dev)
+        rmax = torch.empty(max(ng, 1), dtype=torch.float64, device=dev)
+        vbulk = torch.empty((max(ng, 1), 3), dtype=torch.float64, device=dev) if vel is not None else None
+        cp = p.c()
+        self._check(self.lib.hop_halo_stats(self.h, n, _ptr(pos_d), _ptr(vel_d), _ptr(group), ng,
+                                            _ptr(table), C.byref(cp), _ptr(com), _ptr(rmax),
+                                            _ptr(vbulk), self._stream(stream)))
+        out = {"com": com[:ng], "rmax": rmax[:ng]}
+        if vbulk is not None:
+            out["vbulk"] = vbulk[:ng]
         return out
 
     def sync(self, stream=None):

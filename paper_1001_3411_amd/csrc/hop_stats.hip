@@ -1,0 +1,177 @@
+// hop_stats.hip -- per-halo statistics after the labels: particle count,
+// centre of mass, maximum radius and bulk velocity (the per-task output the
+// paper lists in section 3.1 and section 5).
+//
+// Offsets are integer displacements from each halo's peak particle, the
+// minimum image (representative in [-G/2, G/2)) in a periodic box of side
+// G = 2^grid_bits, so halos straddling the box edge are unwrapped.  Their
+// per-halo sums are 64-bit integer atomics (in LDS per block first for the
+// largest halos), exact in any order; the mean
+// offset is one FP64 division, so the centre is the same in every run.
+// The maximum radius is an atomic maximum over the FP64 bits of each
+// member's distance (non-negative doubles order like their bits).  The
+// velocity sums are FP64 atomics: their order, and so their last bits,
+// vary from run to run within the FP64 summation bound.
+#include "hop_internal.h"
+
+namespace {
+
+__device__ __forceinline__ int64_t min_image(int64_t d, int periodic, int64_t G)
+{
+    if (!periodic) return d;
+    d &= G - 1;  // d mod G in [0, G) (G a power of two, two's complement)
+    return d >= (G >> 1) ? d - G : d;
+}
+
+// Halos are numbered by size, largest first: the members of halos below
+// kPriv are summed in LDS per block and flushed with one global atomic per
+// block and sum, so the largest halos do not serialise on a few addresses.
+constexpr int kPriv = 256;
+constexpr int kStatsBlock = 256;
+
+__global__ void __launch_bounds__(kStatsBlock)
+k_stats_sum(int64_t n, const uint32_t *__restrict__ pos, const float *__restrict__ vel,
+            const int32_t *__restrict__ group, int32_t n_groups,
+            const hop_group_info *__restrict__ groups, int periodic, int64_t G,
+            unsigned long long *__restrict__ osum, double *__restrict__ vsum,
+            uint32_t *__restrict__ dflags)
+{
+    __shared__ unsigned long long lo[kPriv * 3];
+    __shared__ double lv[kPriv * 3];
+    for (int t = threadIdx.x; t < kPriv * 3; t += kStatsBlock) {
+        lo[t] = 0ull;
+        lv[t] = 0.0;
+    }
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t g = i < n ? group[i] : -1;
+    if (g >= n_groups) {
+        atomicOr(dflags, DERR_INDEX);
+        g = -1;
+    }
+    int32_t pk = -1;
+    if (g >= 0) {
+        pk = groups[g].peak;
+        if (pk < 0 || pk >= n) {
+            atomicOr(dflags, DERR_INDEX);
+            g = -1;
+        }
+    }
+    if (g >= 0) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const int64_t d = min_image((int64_t)pos[3 * i + k] - (int64_t)pos[3 * (int64_t)pk + k], periodic, G);
+            const double v = vel ? (double)vel[3 * i + k] : 0.0;
+            if (g < kPriv) {
+                atomicAdd(&lo[3 * g + k], (unsigned long long)d);  // two's complement sum
+                if (vel) atomicAdd(&lv[3 * g + k], v);
+            } else {
+                atomicAdd(&osum[3 * (int64_t)g + k], (unsigned long long)d);
+                if (vel) atomicAdd(&vsum[3 * (int64_t)g + k], v);
+            }
+        }
+    }
+    __syncthreads();
+    const int lim = min(n_groups, kPriv) * 3;
+    for (int t = threadIdx.x; t < lim; t += kStatsBlock) {
+        if (lo[t]) atomicAdd(&osum[t], lo[t]);
+        if (vel && lv[t] != 0.0) atomicAdd(&vsum[t], lv[t]);
+    }
+}
+
+// per halo: mean offset, centre, bulk velocity
+__global__ void k_stats_halo(int32_t n_groups, const uint32_t *__restrict__ pos,
+                             const hop_group_info *__restrict__ groups, int periodic, int64_t G,
+                             const unsigned long long *__restrict__ osum, const double *__restrict__ vsum,
+                             double *__restrict__ mean, double *__restrict__ com, double *__restrict__ vbulk)
+{
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups) return;
+    const double c = (double)groups[g].count;
+    const int64_t p = groups[g].peak;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const double m = (double)(int64_t)osum[3 * g + k] / c;
+        mean[3 * g + k] = m;
+        double x = (double)pos[3 * p + k] + m;
+        if (periodic) {
+            const double Gd = (double)G;
+            x = x < 0.0 ? x + Gd : (x >= Gd ? x - Gd : x);
+        }
+        com[3 * g + k] = x;
+        if (vbulk) vbulk[3 * g + k] = vsum[3 * g + k] / c;
+    }
+}
+
+__global__ void __launch_bounds__(kStatsBlock)
+k_stats_radius(int64_t n, const uint32_t *__restrict__ pos, const int32_t *__restrict__ group,
+               int32_t n_groups, const hop_group_info *__restrict__ groups, int periodic,
+               int64_t G, const double *__restrict__ mean,
+               unsigned long long *__restrict__ rmax_bits)
+{
+    __shared__ unsigned long long lr[kPriv];
+    for (int t = threadIdx.x; t < kPriv; t += kStatsBlock) lr[t] = 0ull;
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t g = i < n ? group[i] : -1;
+    if (g >= n_groups) g = -1;
+    int64_t pk = g >= 0 ? groups[g].peak : -1;
+    if (pk < 0 || pk >= n) g = -1;
+    if (g >= 0) {
+        double e[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const int64_t d = min_image((int64_t)pos[3 * i + k] - (int64_t)pos[3 * pk + k], periodic, G);
+            e[k] = (double)d - mean[3 * (int64_t)g + k];
+        }
+        const double r = __builtin_sqrt((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]);
+        // non-negative doubles order like their bit patterns
+        const unsigned long long rb = (unsigned long long)__double_as_longlong(r);
+        if (g < kPriv) atomicMax(&lr[g], rb);
+        else atomicMax(&rmax_bits[g], rb);
+    }
+    __syncthreads();
+    const int lim = min(n_groups, kPriv);
+    for (int t = threadIdx.x; t < lim; t += kStatsBlock)
+        if (lr[t]) atomicMax(&rmax_bits[t], lr[t]);
+}
+
+}  // namespace
+
+extern "C" int hop_halo_stats(hop_ctx *ctx, int64_t n, const uint32_t *pos, const float *vel,
+                              const int32_t *group, int32_t n_groups, const hop_group_info *groups,
+                              const hop_params *p, double *com, double *rmax, double *vbulk,
+                              void *stream)
+{
+    if (!ctx) return HOP_ERR_ARG;
+    ctx->err.clear();
+    if (!p) return hop_fail(ctx, HOP_ERR_ARG, "params is NULL");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return hop_fail(ctx, HOP_ERR_ARG, "need 1 <= n < 2^31");
+    if (n_groups < 0) return hop_fail(ctx, HOP_ERR_ARG, "n_groups < 0");
+    if (p->grid_bits < 1 || p->grid_bits > 21) return hop_fail(ctx, HOP_ERR_ARG, "grid_bits must be in [1, 21]");
+    if (!pos || !group || (n_groups > 0 && (!groups || !com || !rmax)))
+        return hop_fail(ctx, HOP_ERR_ARG, "pos, group, groups, com and rmax must be non-NULL");
+    if (vel && !vbulk) return hop_fail(ctx, HOP_ERR_ARG, "vbulk must be non-NULL when vel is given");
+    HOPTRY(hop_set_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    if (n_groups == 0) return HOP_OK;
+    const int periodic = (p->flags & HOP_PERIODIC) ? 1 : 0;
+    const int64_t G = (int64_t)1 << p->grid_bits;
+    const size_t g3 = (size_t)n_groups * 3;
+    HOPTRY(hop_reserve(ctx, ctx->work_e, g3 * 8 * 3));  // offset sums, velocity sums, mean offsets
+    unsigned long long *osum = (unsigned long long *)ctx->work_e.ptr;
+    double *vsum = (double *)(osum + g3);
+    double *mean = vsum + g3;
+    HOPCHK(ctx, hipMemsetAsync(osum, 0, g3 * 8 * 2, s));
+    HOPCHK(ctx, hipMemsetAsync(rmax, 0, (size_t)n_groups * 8, s));
+    k_stats_sum<<<hop_grid(n, kStatsBlock), kStatsBlock, 0, s>>>(n, pos, vel, group, n_groups, groups, periodic, G, osum,
+                                                 vel ? vsum : nullptr, (uint32_t *)ctx->flags.ptr);
+    HOPCHK(ctx, hipGetLastError());
+    k_stats_halo<<<hop_grid(n_groups, 256), 256, 0, s>>>(n_groups, pos, groups, periodic, G, osum, vsum,
+                                                         mean, com, vel ? vbulk : nullptr);
+    HOPCHK(ctx, hipGetLastError());
+    k_stats_radius<<<hop_grid(n, kStatsBlock), kStatsBlock, 0, s>>>(n, pos, group, n_groups, groups, periodic, G, mean,
+                                                    (unsigned long long *)rmax);
+    HOPCHK(ctx, hipGetLastError());
+    return HOP_OK;
+}
