@@ -205,6 +205,23 @@ def bench_box(args):
     log(f"{args.steps} steps: {ms_step:.2f} ms/step, knn {np.mean(knn_ms):.2f} ms, "
         f"sort+tree {np.mean(sort_ms):.2f} ms, groups={groups} chains={chains}")
     roofline = knn_roofline(n, float(np.mean(knn_ms)), "k_knn_density", value, fused=True)
+    # per-halo statistics of the last step's labels (an output after the
+    # path, outside the timed step): centre, maximum radius, and the bulk
+    # velocity of a seeded synthetic velocity field
+    gen = torch.Generator(device=dev).manual_seed(7)
+    vel = torch.randn((n, 3), generator=gen, device=dev, dtype=torch.float32) * 300.0
+    ctx.halo_stats(pos, out["group"], out["table"], prm, vel=vel, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(3):
+        ctx.halo_stats(pos, out["group"], out["table"], prm, vel=vel, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    halo_ms = e0.elapsed_time(e1) / 3
+    del vel
+    log(f"halo statistics: {groups} halos, {halo_ms:.2f} ms")
+    halo = {"ms": round(halo_ms, 3), "halos": groups,
+            "bytes_per_particle": 56, "achieved_gbs": round(56 * n / (halo_ms / 1e3) / 1e9, 2)}
     search = None
     if args.search == "compare":
         from dataclasses import replace
@@ -267,7 +284,8 @@ def bench_box(args):
             "config": {"workload": p.name, "n": n, "n_dens": prm.n_dens, "n_hop": prm.n_hop,
                        "n_merge": prm.n_merge, "k_store": prm.k_store, "periodic": p.periodic,
                        "search": "plain", "groups": groups, "chains": chains},
-            "roofline": roofline, "cpu_baseline": cpu, "search_compare": search}
+            "roofline": roofline, "halo_stats": halo,
+            "cpu_baseline": cpu, "search_compare": search}
 
 
 def bench_batch(args):

@@ -12,6 +12,8 @@
 // member's distance (non-negative doubles order like their bits).  The
 // velocity sums are FP64 atomics: their order, and so their last bits,
 // vary from run to run within the FP64 summation bound.
+#include <algorithm>
+
 #include "hop_internal.h"
 
 namespace {
@@ -26,7 +28,9 @@ __device__ __forceinline__ int64_t min_image(int64_t d, int periodic, int64_t G)
 // Halos are numbered by size, largest first: the members of halos below
 // kPriv are summed in LDS per block and flushed with one global atomic per
 // block and sum, so the largest halos do not serialise on a few addresses.
-constexpr int kPriv = 256;
+// The blocks stride over the particles (a fixed grid), so each block's
+// flush is paid once for many particles.
+constexpr int kPriv = 1024;
 constexpr int kStatsBlock = 256;
 
 __global__ void __launch_bounds__(kStatsBlock)
@@ -43,21 +47,19 @@ k_stats_sum(int64_t n, const uint32_t *__restrict__ pos, const float *__restrict
         lv[t] = 0.0;
     }
     __syncthreads();
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t g = i < n ? group[i] : -1;
-    if (g >= n_groups) {
-        atomicOr(dflags, DERR_INDEX);
-        g = -1;
-    }
-    int32_t pk = -1;
-    if (g >= 0) {
-        pk = groups[g].peak;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t g = group[i];
+        if (g < 0) continue;
+        if (g >= n_groups) {
+            atomicOr(dflags, DERR_INDEX);
+            continue;
+        }
+        const int32_t pk = groups[g].peak;
         if (pk < 0 || pk >= n) {
             atomicOr(dflags, DERR_INDEX);
-            g = -1;
+            continue;
         }
-    }
-    if (g >= 0) {
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             const int64_t d = min_image((int64_t)pos[3 * i + k] - (int64_t)pos[3 * (int64_t)pk + k], periodic, G);
@@ -112,12 +114,12 @@ k_stats_radius(int64_t n, const uint32_t *__restrict__ pos, const int32_t *__res
     __shared__ unsigned long long lr[kPriv];
     for (int t = threadIdx.x; t < kPriv; t += kStatsBlock) lr[t] = 0ull;
     __syncthreads();
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t g = i < n ? group[i] : -1;
-    if (g >= n_groups) g = -1;
-    int64_t pk = g >= 0 ? groups[g].peak : -1;
-    if (pk < 0 || pk >= n) g = -1;
-    if (g >= 0) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t g = group[i];
+        if (g < 0 || g >= n_groups) continue;
+        const int64_t pk = groups[g].peak;
+        if (pk < 0 || pk >= n) continue;
         double e[3];
 #pragma unroll
         for (int k = 0; k < 3; k++) {
@@ -164,13 +166,14 @@ extern "C" int hop_halo_stats(hop_ctx *ctx, int64_t n, const uint32_t *pos, cons
     double *mean = vsum + g3;
     HOPCHK(ctx, hipMemsetAsync(osum, 0, g3 * 8 * 2, s));
     HOPCHK(ctx, hipMemsetAsync(rmax, 0, (size_t)n_groups * 8, s));
-    k_stats_sum<<<hop_grid(n, kStatsBlock), kStatsBlock, 0, s>>>(n, pos, vel, group, n_groups, groups, periodic, G, osum,
+    const int grid = (int)std::min<int64_t>(hop_grid(n, kStatsBlock), (int64_t)ctx->n_cu * 8);
+    k_stats_sum<<<grid, kStatsBlock, 0, s>>>(n, pos, vel, group, n_groups, groups, periodic, G, osum,
                                                  vel ? vsum : nullptr, (uint32_t *)ctx->flags.ptr);
     HOPCHK(ctx, hipGetLastError());
     k_stats_halo<<<hop_grid(n_groups, 256), 256, 0, s>>>(n_groups, pos, groups, periodic, G, osum, vsum,
                                                          mean, com, vel ? vbulk : nullptr);
     HOPCHK(ctx, hipGetLastError());
-    k_stats_radius<<<hop_grid(n, kStatsBlock), kStatsBlock, 0, s>>>(n, pos, group, n_groups, groups, periodic, G, mean,
+    k_stats_radius<<<grid, kStatsBlock, 0, s>>>(n, pos, group, n_groups, groups, periodic, G, mean,
                                                     (unsigned long long *)rmax);
     HOPCHK(ctx, hipGetLastError());
     return HOP_OK;
