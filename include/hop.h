@@ -12,6 +12,7 @@
  *   hop_merge    boundary table, proto-halo and sub-peak merge,
  *                group labels                                        (sec. 2, merge steps 2-5;
  *                                                                     sec. 3.1 last step)
+ *   hop_stitch   whole-box density and lists from padded subvolumes (sec. 3.1)
  *   hop_halo_stats  per-halo count, centre, maximum radius, bulk velocity
  *                (sec. 3.1 output step)
  *
@@ -234,6 +235,33 @@ int hop_merge(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density
               const int32_t *root, const int32_t *chain_of, int32_t n_chains, const int64_t *id,
               const uint8_t *padded, const hop_params *p, int32_t *group, int32_t *n_groups,
               hop_group_info *groups, void *stream);
+
+/*
+ * hop_stitch -- whole-box density and neighbour lists from padded
+ * subvolumes (section 3.1: each task's local particles, given enough
+ * padding, have their whole-box neighbours and density; the tasks' results
+ * are then joined).  On one GPU the join is a scatter: every row of the
+ * batched call that is not padding writes its density and its list,
+ * mapped from subvolume rows to box indices, at its box index; the box's
+ * links, chains, boundaries and groups then come from hop_link, hop_groups
+ * and hop_merge on these arrays.  With every local particle's neighbour
+ * sphere inside its padded subvolume, and each subvolume's rows in
+ * increasing box index (so ties go the same way), the result equals the
+ * whole-box run.
+ *
+ * offsets    HOST [n_sub + 1] row ranges of the batch, offsets[0] = 0
+ * index      [rows] int64: the box index of each batch row
+ * padded     [rows] uint8 or NULL (nonzero rows are skipped)
+ * density_b  [rows], nbr_b [rows][k_store]: hop_run_batch outputs (rows
+ *            local to their subvolume)
+ * density    [n] output; nbr [n][k_store] output or NULL
+ * Every box index must be the core row of exactly one subvolume (else its
+ * outputs are not written).  Synchronises `stream`; a box index or list
+ * entry out of range is HOP_ERR_RANGE.
+ */
+int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, const int64_t *index,
+               const uint8_t *padded, const double *density_b, const int32_t *nbr_b,
+               int32_t k_store, int64_t n, double *density, int32_t *nbr, void *stream);
 
 /*
  * hop_halo_stats -- per-halo statistics (section 3.1, the output step: each

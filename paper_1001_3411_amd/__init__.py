@@ -116,6 +116,7 @@ def load():
     L.hop_merge.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, C.POINTER(_Params), vp,
                             C.POINTER(i32), vp, vp]
     L.hop_halo_stats.argtypes = [vp, i64, vp, vp, vp, i32, vp, C.POINTER(_Params), vp, vp, vp, vp]
+    L.hop_stitch.argtypes = [vp, i32, vp, vp, vp, vp, vp, i32, i64, vp, vp, vp]
     L.hop_run_batch.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(_Params), vp, vp, vp, vp, vp,
                                 vp, vp, vp, vp, vp, vp]
     f32 = C.c_float
@@ -280,6 +281,22 @@ class HopContext:
             out["g_peak"] = (t[:, 1] & 0xFFFFFFFF).to(torch.int32)
             out["g_peak_dens"] = t[:, 2].contiguous().view(torch.float64)
         return out
+
+    def stitch(self, offsets, index, padded, density_b, nbr_b, n, k_store=64, stream=None):
+        """hop_stitch: box density [n] and lists [n][k_store] from the batched
+        call's rows (offsets host, index/padded per row)."""
+        import numpy as np
+        torch = self._torch
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        idx_d = self._dev(index, torch.int64)
+        pad_d = self._dev(padded, torch.uint8)
+        dev = density_b.device
+        dens = torch.empty(n, dtype=torch.float64, device=dev)
+        nbr = torch.empty((n, k_store), dtype=torch.int32, device=dev) if nbr_b is not None else None
+        self._check(self.lib.hop_stitch(self.h, off.size - 1, off.ctypes.data_as(C.c_void_p), _ptr(idx_d),
+                                        _ptr(pad_d), _ptr(density_b), _ptr(nbr_b), int(k_store), int(n),
+                                        _ptr(dens), _ptr(nbr), self._stream(stream)))
+        return dens, nbr
 
     def halo_stats(self, pos, group, table, params: HopParams | None = None, vel=None,
                    stream=None):

@@ -60,3 +60,41 @@ def test_padded_subvolumes_reproduce_box_densities(ctx):
               f"{int(np.count_nonzero(dens_b[rows[~fits]] != dens_full[gi[~fits]]))} of the "
               f"{int((~fits).sum())} near the edge differ", flush=True)
     assert checked > 0.9 * p.n
+
+
+def test_stitched_pipeline_equals_whole_box(ctx):
+    """Decompose, run the subvolumes in one batched call, stitch their core
+    rows into box arrays (hop_stitch), and run links, chains and the merge
+    on the box: every output equals the whole-box run."""
+    import time
+
+    import torch
+
+    from paper_1001_3411_amd import HopParams
+    from paper_1001_3411_amd.decompose import decompose
+    p = synth.config(2)
+    full = HopParams(mean_density=p.mean_density)
+    ref = ctx.run(p.pos, full)
+    d = decompose(p.pos, 8, seed=3)
+    sub = HopParams(periodic=False, padded_rules=True, mean_density=p.mean_density)
+    pos_b = torch.from_numpy(d.pos.view(np.int32)).cuda()
+    pad_b = torch.from_numpy(d.padded).cuda()
+    idx_b = torch.from_numpy(d.index).cuda()
+    md = np.full(8, p.mean_density)
+    for rep in range(2):   # the second pass is timed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = ctx.run_batch(pos_b, d.offsets, sub, padded=pad_b, mean_density=md)
+        dens, nbr = ctx.stitch(d.offsets, idx_b, pad_b, out["density"], out["nbr"], p.n)
+        hop = ctx.link(nbr, dens, full)
+        root, chain_of, nc = ctx.groups(hop, dens, full)
+        m = ctx.merge(nbr, dens, root, chain_of, nc, full)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    print(f"[stitch] {p.n} particles, 8 subvolumes ({d.pos.shape[0]} rows with padding): "
+          f"{dt * 1e3:.1f} ms; {m['n_groups']} groups", flush=True)
+    for k, a in (("density", dens), ("nbr", nbr), ("hop", hop), ("root", root),
+                 ("chain_of", chain_of), ("group", m["group"]), ("g_count", m["g_count"]),
+                 ("g_peak", m["g_peak"])):
+        assert torch.equal(a, ref[k]), k
+    assert nc == ref["n_chains"] and m["n_groups"] == ref["n_groups"]
