@@ -158,7 +158,7 @@ void hop_ctx_destroy(hop_ctx *ctx)
                       &ctx->work_f, &ctx->hash_keys, &ctx->hash_vals, &ctx->edges_lo,
                       &ctx->edges_hi, &ctx->edges_s, &ctx->batch_tab, &ctx->batch_aux,
                       &ctx->cell_counts, &ctx->cell_r, &ctx->radius_w, &ctx->mlp_part, &ctx->miss,
-                      &ctx->srt_nbr, &ctx->srt_dens};
+                      &ctx->srt_nbr, &ctx->srt_dens, &ctx->jump_done};
     for (DevBuf *b : bufs)
         if (b->ptr) hipFree(b->ptr);
     if (ctx->hflags) hipHostFree(ctx->hflags);

@@ -75,6 +75,7 @@ struct hop_ctx {
     DevBuf radius_w, mlp_part;    // BF16 model weights; training partial sums
     DevBuf miss;                  // learned radius: per-bucket lanes to search again
     DevBuf srt_nbr, srt_dens;     // density + links: sorted copies of list heads and densities
+    DevBuf jump_done;             // chains: particles whose root is final
     int radius_kind = 0;          // HOP_RADIUS_* of the loaded model, 0 = none
     float radius_margin = 0.0f;
     float radius_occupancy = 8.0f;

@@ -72,9 +72,10 @@ __global__ void k_hop(int64_t n, const int32_t *__restrict__ nbr, int k_store, i
 // The same links in Morton order: thread t takes the particle at sorted
 // position t, its first 16 list entries from the sorted copy (one 64-byte
 // row, consecutive threads on consecutive rows; entry 0 is the particle
-// itself) and its density from the sorted copy; the neighbours' densities are gathered from the input-order
-// array, where the 64 threads of a wave, being neighbours in space, mostly
-// gather the same entries.  Same comparisons in the same order as k_hop.
+// itself) and its density from the sorted copy; the neighbours' densities
+// are gathered from the input-order array, where the 64 threads of a wave,
+// being neighbours in space, mostly gather the same entries.  Same
+// comparisons in the same order as k_hop.
 __global__ void k_hop_sorted(int64_t n, const int32_t *__restrict__ nbr16s, int n_hop,
                              const double *__restrict__ dens_s, const double *__restrict__ dens,
                              const int32_t *__restrict__ tk, const uint8_t *__restrict__ padded,
@@ -139,23 +140,33 @@ __global__ void k_root_init(int64_t n, const int32_t *__restrict__ hop, int32_t 
     root[i] = h;
 }
 
-// Up to 4 jumps per launch; *changed is set when a root moved.
-__global__ void k_jump(int64_t n, int32_t *__restrict__ root, uint32_t *__restrict__ changed)
+// Up to 4 jumps per launch; *changed is set when a root moved.  A particle
+// whose root is found self-linked is marked done, and later launches skip
+// it with a one-byte read instead of a random gather (most chains resolve
+// in the first launch).
+__global__ void k_jump(int64_t n, int32_t *__restrict__ root, uint8_t *__restrict__ done,
+                       uint32_t *__restrict__ changed)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (done[i]) return;
     int32_t r = root[i];
     int32_t r0 = r;
+    bool fin = false;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         int32_t rr = root[r];
-        if (rr == r) break;
+        if (rr == r) {
+            fin = true;
+            break;
+        }
         r = rr;
     }
     if (r != r0) {
         root[i] = r;
         *changed = 1u;
     }
+    if (fin) done[i] = 1;
 }
 
 __global__ void k_chain_flags(int64_t n, const int32_t *__restrict__ root,
@@ -234,10 +245,13 @@ int hop_groups_impl(hop_ctx *ctx, int64_t n, const int32_t *hop, const double *d
     uint32_t *total = dflags + 2;
     k_root_init<<<hop_grid(n, 256), 256, 0, s>>>(n, hop, root, dflags);
     HOPCHK(ctx, hipGetLastError());
+    HOPTRY(hop_reserve(ctx, ctx->jump_done, (size_t)n));
+    uint8_t *done = (uint8_t *)ctx->jump_done.ptr;
+    HOPCHK(ctx, hipMemsetAsync(done, 0, (size_t)n, s));
     int rounds = 0;
     for (;;) {
         HOPCHK(ctx, hipMemsetAsync(changed, 0, 4, s));
-        k_jump<<<hop_grid(n, 256), 256, 0, s>>>(n, root, changed);
+        k_jump<<<hop_grid(n, 256), 256, 0, s>>>(n, root, done, changed);
         HOPCHK(ctx, hipGetLastError());
         HOPCHK(ctx, hipMemcpyAsync(ctx->hflags, changed, 4, hipMemcpyDeviceToHost, s));
         HOPCHK(ctx, hipStreamSynchronize(s));
