@@ -450,3 +450,85 @@ def test_padded_particles_get_no_group(orc):
     pad = p.padded.astype(bool)
     assert np.all(r.group[pad] == -1)
     assert np.all(r.hop[pad] == np.flatnonzero(pad))
+
+
+# --------------------------------------------------------------------------
+# labels: the group order (count desc, peak density desc, peak id asc) and
+# the padded-only rule, on hand-built chain tables whose expected numbering
+# is written out by hand
+# --------------------------------------------------------------------------
+
+def test_labels_equal_counts_order_by_peak_density(orc):
+    # three one-chain halos of two particles each; chain peaks 300, 500, 400
+    chain_of = np.array([0, 0, 1, 1, 2, 2], np.int32)
+    chain_root = np.array([0, 2, 4], np.int32)
+    chain_peak = np.array([300.0, 500.0, 400.0])
+    chain_halo = np.array([0, 1, 2], np.int32)
+    group, gc, gp, gd = orc.labels(chain_of, chain_root, chain_peak, chain_halo)
+    # densest peak first: chain 1 -> 0, chain 2 -> 1, chain 0 -> 2
+    assert group.tolist() == [2, 2, 0, 0, 1, 1]
+    assert gc.tolist() == [2, 2, 2]
+    assert gp.tolist() == [2, 4, 0]
+    assert gd.tolist() == [500.0, 400.0, 300.0]
+
+
+def test_labels_count_comes_before_peak_density(orc):
+    # halo of chain 0: 3 particles, peak 250; halo of chain 1: 2 particles,
+    # peak 900 -- the larger halo is number 0 although its peak is lower
+    chain_of = np.array([0, 0, 0, 1, 1], np.int32)
+    group, gc, gp, gd = orc.labels(chain_of, np.array([1, 3], np.int32),
+                                   np.array([250.0, 900.0]), np.array([0, 1], np.int32))
+    assert group.tolist() == [0, 0, 0, 1, 1]
+    assert gc.tolist() == [3, 2] and gp.tolist() == [1, 3]
+
+
+def test_labels_equal_counts_and_peaks_order_by_peak_id(orc):
+    # equal counts and equal peak densities: the peak with the smaller id
+    # comes first; without ids the index decides, with ids the ids decide
+    chain_of = np.array([0, 1, 2, 0, 1, 2], np.int32)
+    chain_root = np.array([3, 1, 5], np.int32)
+    chain_peak = np.array([300.0, 300.0, 300.0])
+    chain_halo = np.array([0, 1, 2], np.int32)
+    group, _, gp, _ = orc.labels(chain_of, chain_root, chain_peak, chain_halo)
+    # peaks by index: 1 (chain 1) -> 0, 3 (chain 0) -> 1, 5 (chain 2) -> 2
+    assert gp.tolist() == [1, 3, 5]
+    assert group.tolist() == [1, 0, 2, 1, 0, 2]
+    ids = np.array([60, 50, 40, 30, 20, 10], np.int64)
+    group, _, gp, _ = orc.labels(chain_of, chain_root, chain_peak, chain_halo, ids=ids)
+    # ids of the peaks: 5 -> 10, 3 -> 30, 1 -> 50, so chain 2 -> 0,
+    # chain 0 -> 1, chain 1 -> 2
+    assert gp.tolist() == [5, 3, 1]
+    assert group.tolist() == [1, 2, 0, 1, 2, 0]
+
+
+def test_labels_halo_peak_is_its_densest_chain(orc):
+    # one halo of chains 0 and 1 (peaks 250 and 600), one halo of chain 2
+    # (peak 450); equal counts, so the first halo's peak (600) puts it first
+    chain_of = np.array([0, 1, 2, 2], np.int32)
+    chain_root = np.array([0, 1, 3], np.int32)
+    chain_peak = np.array([250.0, 600.0, 450.0])
+    chain_halo = np.array([0, 0, 2], np.int32)
+    group, gc, gp, gd = orc.labels(chain_of, chain_root, chain_peak, chain_halo)
+    assert group.tolist() == [0, 0, 1, 1]
+    assert gp.tolist() == [1, 3] and gd.tolist() == [600.0, 450.0]
+
+
+def test_labels_padded_only_halo_gets_no_number(orc):
+    # halo of chain 0: particles 0, 1 (both padded); halo of chain 1:
+    # particles 2, 3, 4 with 3 and 4 padded (one labelled member); halo of
+    # chain 2: particles 5, 6 (two labelled members); particle 7 unchained
+    chain_of = np.array([0, 0, 1, 1, 1, 2, 2, -1], np.int32)
+    chain_root = np.array([0, 2, 5], np.int32)
+    chain_peak = np.array([900.0, 800.0, 300.0])
+    chain_halo = np.array([0, 1, 2], np.int32)
+    padded = np.array([1, 1, 0, 1, 1, 0, 0, 0], np.uint8)
+    group, gc, gp, _ = orc.labels(chain_of, chain_root, chain_peak, chain_halo,
+                                  padded=padded, padded_rules=True)
+    # chain 0's halo has no unpadded member: no number; chain 2's halo (2
+    # members) precedes chain 1's (1 member) despite the lower peak
+    assert group.tolist() == [-1, -1, 1, -1, -1, 0, 0, -1]
+    assert gc.tolist() == [2, 1] and gp.tolist() == [5, 2]
+    # without the padded rules every halo counts all its members
+    group, gc, _, _ = orc.labels(chain_of, chain_root, chain_peak, chain_halo, padded=padded)
+    assert group.tolist() == [1, 1, 0, 0, 0, 2, 2, -1]
+    assert gc.tolist() == [3, 2, 2]
