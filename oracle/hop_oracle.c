@@ -333,6 +333,29 @@ static void kd_search(const kdtree_t *t, int64_t node, int64_t q, kheap_t *h)
     if (h->size < h->cap || db <= h->e[0].d2) kd_search(t, b, q, h);
 }
 
+/* build the tree over all n particles (t->s must be set) */
+static int kd_make(kdtree_t *t, int64_t n)
+{
+    t->idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    /* every bucket holds at least KD_BUCKET/2 points, so nodes < n/4 + 2 */
+    t->nodes = (kdnode_t *)malloc(sizeof(kdnode_t) * (size_t)(n / 2 + 16));
+    t->n_nodes = 0;
+    if (!t->idx || !t->nodes) {
+        free(t->idx);
+        free(t->nodes);
+        return ORC_ERR_NOMEM;
+    }
+    for (int64_t i = 0; i < n; i++) t->idx[i] = i;
+    kd_build(t, 0, n);
+    return ORC_OK;
+}
+
+static void kd_free(kdtree_t *t)
+{
+    free(t->idx);
+    free(t->nodes);
+}
+
 int orc_knn_kdtree(int64_t n, const uint32_t *pos, const int64_t *id, int periodic,
                    int grid_bits, int k, const int64_t *queries, int64_t nq,
                    int32_t *nbr, int64_t *d2)
@@ -343,13 +366,8 @@ int orc_knn_kdtree(int64_t n, const uint32_t *pos, const int64_t *id, int period
                  (uint64_t)1 << grid_bits};
     kdtree_t t;
     t.s = &s;
-    t.idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    /* every bucket holds at least KD_BUCKET/2 points, so nodes < n/4 + 2 */
-    t.nodes = (kdnode_t *)malloc(sizeof(kdnode_t) * (size_t)(n / 2 + 16));
-    t.n_nodes = 0;
-    if (!t.idx || !t.nodes) { free(t.idx); free(t.nodes); return ORC_ERR_NOMEM; }
-    for (int64_t i = 0; i < n; i++) t.idx[i] = i;
-    kd_build(&t, 0, n);
+    int err = kd_make(&t, n);
+    if (err) return err;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t r = 0; r < nq; r++) {
         int64_t q = queries ? queries[r] : r;
@@ -359,8 +377,7 @@ int orc_knn_kdtree(int64_t n, const uint32_t *pos, const int64_t *id, int period
         kd_search(&t, 0, q, &h);
         kheap_emit(&h, q, k, nbr + r * k, d2 ? d2 + r * k : NULL);
     }
-    free(t.idx);
-    free(t.nodes);
+    kd_free(&t);
     return ORC_OK;
 }
 
@@ -772,6 +789,53 @@ int orc_labels(int64_t n, const int32_t *chain_of, int64_t n_chains, const int32
 /* ------------------------------------------------------------------------ */
 
 /*
+ * Stages 3-7 (links, chains, boundaries, merge, labels) from the densities
+ * and the first k_cols list columns (k_cols >= n_hop, n_merge).
+ */
+static int run_stages(int64_t n, const int64_t *id, const uint8_t *padded, int n_hop,
+                      int n_merge, int k_cols, double delta_outer, double delta_saddle,
+                      double delta_peak, int padded_rules, const double *dens,
+                      const int32_t *nbr, int32_t *hop, int32_t *root, int32_t *chain_of,
+                      int32_t *group, int64_t *g_count, int32_t *g_peak, double *g_peak_dens,
+                      int64_t *counts)
+{
+    int err = orc_hop(n, k_cols, n_hop, nbr, dens, id, padded, padded_rules, hop);
+    if (err) return err;
+    int32_t *chain_root = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    double *chain_peak = (double *)malloc(sizeof(double) * (size_t)n);
+    int64_t cap = (int64_t)n * (n_merge > 1 ? n_merge - 1 : 1) + 1;
+    int32_t *e_lo = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    int32_t *e_hi = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    double *e_s = (double *)malloc(sizeof(double) * (size_t)cap);
+    int32_t *chain_halo = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t C = 0, E = 0, G = 0;
+    if (!chain_root || !chain_peak || !e_lo || !e_hi || !e_s || !chain_halo) {
+        err = ORC_ERR_NOMEM;
+        goto done;
+    }
+    err = orc_chains(n, hop, dens, id, delta_outer, root, chain_of, chain_root, chain_peak, &C);
+    if (err) goto done;
+    err = orc_saddles(n, k_cols, n_merge, nbr, dens, chain_of, padded, padded_rules, e_lo, e_hi,
+                      e_s, cap, &E);
+    if (err) goto done;
+    err = orc_merge(C, chain_peak, E, e_lo, e_hi, e_s, delta_saddle, delta_peak, chain_halo);
+    if (err) goto done;
+    err = orc_labels(n, chain_of, C, chain_root, chain_peak, chain_halo, id, padded, padded_rules,
+                     group, &G, g_count, g_peak, g_peak_dens);
+done:
+    counts[0] = C;
+    counts[1] = E;
+    counts[2] = G;
+    free(chain_root);
+    free(chain_peak);
+    free(e_lo);
+    free(e_hi);
+    free(e_s);
+    free(chain_halo);
+    return err;
+}
+
+/*
  * Runs stages 1-7 for all particles.  search: 0 = brute force, 1 = kd-tree.
  * Output arrays are caller-owned: dens[n], nbr[n*k_store], hop[n], root[n],
  * chain_of[n], group[n], and g_count/g_peak/g_peak_dens with room for n.
@@ -801,40 +865,153 @@ int orc_run(int64_t n, const uint32_t *pos, const int64_t *id, const uint8_t *pa
     for (int64_t i = 0; i < n; i++)
         memcpy(nbr + i * k_store, full + i * k, sizeof(int32_t) * (size_t)k_store);
     free(full);
-    err = orc_hop(n, k_store, n_hop, nbr, dens, id, padded, padded_rules, hop);
-    if (err) return err;
-    int32_t *chain_root = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    double *chain_peak = (double *)malloc(sizeof(double) * (size_t)n);
-    int64_t cap = (int64_t)n * (n_merge > 1 ? n_merge - 1 : 1) + 1;
-    int32_t *e_lo = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
-    int32_t *e_hi = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
-    double *e_s = (double *)malloc(sizeof(double) * (size_t)cap);
-    int32_t *chain_halo = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    int64_t C = 0, E = 0, G = 0;
-    if (!chain_root || !chain_peak || !e_lo || !e_hi || !e_s || !chain_halo) {
-        err = ORC_ERR_NOMEM;
-        goto done;
+    return run_stages(n, id, padded, n_hop, n_merge, k_store, delta_outer, delta_saddle,
+                      delta_peak, padded_rules, dens, nbr, hop, root, chain_of, group, g_count,
+                      g_peak, g_peak_dens, counts);
+}
+
+/*
+ * Word-wise FNV-1a over a list row (offset basis 0xcbf29ce484222325, prime
+ * 0x100000001b3, one step per 32-bit entry): a fingerprint of a row kept
+ * when the row itself is too long to keep for every particle.
+ */
+static uint64_t row_fnv1a(const int32_t *row, int k)
+{
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (int t = 0; t < k; t++) {
+        h ^= (uint64_t)(uint32_t)row[t];
+        h *= 0x100000001b3ull;
     }
-    err = orc_chains(n, hop, dens, id, delta_outer, root, chain_of, chain_root, chain_peak, &C);
-    if (err) goto done;
-    err = orc_saddles(n, k_store, n_merge, nbr, dens, chain_of, padded, padded_rules, e_lo, e_hi,
-                      e_s, cap, &E);
-    if (err) goto done;
-    err = orc_merge(C, chain_peak, E, e_lo, e_hi, e_s, delta_saddle, delta_peak, chain_halo);
-    if (err) goto done;
-    err = orc_labels(n, chain_of, C, chain_root, chain_peak, chain_halo, id, padded, padded_rules,
-                     group, &G, g_count, g_peak, g_peak_dens);
-done:
-    counts[0] = C;
-    counts[1] = E;
-    counts[2] = G;
-    free(chain_root);
-    free(chain_peak);
-    free(e_lo);
-    free(e_hi);
-    free(e_s);
-    free(chain_halo);
+    return h;
+}
+
+/*
+ * The same pipeline as orc_run in bounded memory, for boxes whose n x N_dens
+ * lists do not fit: the kd-tree is built once (orc_lite_begin) and queried
+ * in pieces (orc_lite_query, by ranges of the tree's leaf order, which only
+ * changes which particles share a piece); each piece's full lists give the
+ * densities and are then reduced to
+ *   nbr[n][k_keep]   the first k_keep entries of every list (k_keep >= n_hop,
+ *                    n_merge: the later stages read nothing else),
+ *   row_hash[n]      row_fnv1a of the first k_store entries,
+ *   r2max[n]         (optional) d^2 to the N_dens-th entry.
+ * Stages 3-7 then run as in orc_run on the kept columns (orc_stages), so
+ * every output equals orc_run's (the list columns by their fingerprint).
+ * The caller keeps pos and id alive until orc_lite_end.
+ */
+typedef struct {
+    space_t s;
+    kdtree_t t;
+    int k, k_store, k_keep;
+    double norm;
+} orc_lite_t;
+
+void *orc_lite_begin(int64_t n, const uint32_t *pos, const int64_t *id, int periodic,
+                     int grid_bits, int n_dens, int k_store, int k_keep, double mean_density)
+{
+    if (!(1 <= k_keep && k_keep <= k_store && k_store <= n_dens && n_dens <= ORC_MAX_K))
+        return NULL;
+    if (n < n_dens || grid_bits < 1 || grid_bits > 21 || !(mean_density > 0)) return NULL;
+    orc_lite_t *L = (orc_lite_t *)calloc(1, sizeof(orc_lite_t));
+    if (!L) return NULL;
+    space_t s = {pos, id, n, periodic, (uint32_t)((1u << grid_bits) - 1u),
+                 (uint64_t)1 << grid_bits};
+    L->s = s;
+    L->t.s = &L->s;
+    L->k = n_dens;
+    L->k_store = k_store;
+    L->k_keep = k_keep;
+    L->norm = orc_norm(mean_density);
+    if (kd_make(&L->t, n)) {
+        free(L);
+        return NULL;
+    }
+    return L;
+}
+
+/* the particles at tree positions [c0, c1); outputs indexed by particle */
+int orc_lite_query(void *h, int64_t c0, int64_t c1, double *dens, int32_t *nbr,
+                   uint64_t *row_hash, int64_t *r2max)
+{
+    orc_lite_t *L = (orc_lite_t *)h;
+    if (!L || c0 < 0 || c1 > L->s.n || c0 > c1) return ORC_ERR_ARG;
+    const int k = L->k;
+    const int64_t m = c1 - c0;
+    int32_t *full = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1) * (size_t)k);
+    int64_t *d2 = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1) * (size_t)k);
+    if (!full || !d2) {
+        free(full);
+        free(d2);
+        return ORC_ERR_NOMEM;
+    }
+    int err = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < m; r++) {
+        const int64_t q = L->t.idx[c0 + r];
+        kheap_t hp;
+        hp.size = 0;
+        hp.cap = k - 1;
+        kd_search(&L->t, 0, q, &hp);
+        int32_t *row = full + r * k;
+        int64_t *drow = d2 + r * k;
+        kheap_emit(&hp, q, k, row, drow);
+        int e = density_one(drow, k, L->norm, &dens[q]);
+        if (e) {
+#pragma omp atomic write
+            err = e;
+        }
+        row_hash[q] = row_fnv1a(row, L->k_store);
+        memcpy(nbr + q * L->k_keep, row, sizeof(int32_t) * (size_t)L->k_keep);
+        if (r2max) r2max[q] = drow[k - 1];
+    }
+    free(full);
+    free(d2);
     return err;
+}
+
+void orc_lite_end(void *h)
+{
+    orc_lite_t *L = (orc_lite_t *)h;
+    if (!L) return;
+    kd_free(&L->t);
+    free(L);
+}
+
+/* stages 3-7 from densities and the first k_cols list columns */
+int orc_stages(int64_t n, const int64_t *id, const uint8_t *padded, int n_hop, int n_merge,
+               int k_cols, double delta_outer, double delta_saddle, double delta_peak,
+               int padded_rules, const double *dens, const int32_t *nbr, int32_t *hop,
+               int32_t *root, int32_t *chain_of, int32_t *group, int64_t *g_count,
+               int32_t *g_peak, double *g_peak_dens, int64_t *counts)
+{
+    if (!(1 <= n_merge && n_merge <= n_hop && n_hop <= k_cols && k_cols <= ORC_MAX_K))
+        return ORC_ERR_ARG;
+    return run_stages(n, id, padded, n_hop, n_merge, k_cols, delta_outer, delta_saddle,
+                      delta_peak, padded_rules, dens, nbr, hop, root, chain_of, group, g_count,
+                      g_peak, g_peak_dens, counts);
+}
+
+/* all of the above in one call, in pieces of `chunk` particles */
+int orc_run_lite(int64_t n, const uint32_t *pos, const int64_t *id, const uint8_t *padded,
+                 int periodic, int grid_bits, int n_dens, int n_hop, int n_merge, int k_store,
+                 int k_keep, double delta_outer, double delta_saddle, double delta_peak,
+                 double mean_density, int padded_rules, int64_t chunk,
+                 double *dens, int32_t *nbr, uint64_t *row_hash, int64_t *r2max,
+                 int32_t *hop, int32_t *root, int32_t *chain_of, int32_t *group,
+                 int64_t *g_count, int32_t *g_peak, double *g_peak_dens, int64_t *counts)
+{
+    if (!(1 <= n_merge && n_merge <= n_hop && n_hop <= k_keep) || chunk < 1) return ORC_ERR_ARG;
+    void *L = orc_lite_begin(n, pos, id, periodic, grid_bits, n_dens, k_store, k_keep,
+                             mean_density);
+    if (!L) return ORC_ERR_ARG;
+    int err = ORC_OK;
+    for (int64_t c0 = 0; c0 < n && !err; c0 += chunk)
+        err = orc_lite_query(L, c0, n - c0 < chunk ? n : c0 + chunk, dens, nbr, row_hash, r2max);
+    orc_lite_end(L);
+    if (err) return err;
+    return orc_stages(n, id, padded, n_hop, n_merge, k_keep, delta_outer, delta_saddle,
+                      delta_peak, padded_rules, dens, nbr, hop, root, chain_of, group, g_count,
+                      g_peak, g_peak_dens, counts);
 }
 
 int orc_num_threads(void)

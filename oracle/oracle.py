@@ -16,7 +16,8 @@ from . import build as _build
 
 __all__ = [
     "lib", "knn", "density", "norm", "hop", "chains", "saddles", "merge", "labels",
-    "run", "OracleResult", "num_threads", "HopParams",
+    "run", "run_lite", "Lite", "stages", "OracleResult", "LiteResult", "num_threads",
+    "HopParams",
 ]
 
 _LIB = None
@@ -42,6 +43,16 @@ def lib():
         L.orc_labels.argtypes = [i64, vp, i64, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
         L.orc_run.argtypes = [i64, vp, vp, vp, i32, i32, i32, i32, i32, i32, f64, f64, f64, f64,
                               i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_run_lite.argtypes = [i64, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, f64, f64,
+                                   f64, f64, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                   vp, vp]
+        L.orc_lite_begin.argtypes = [i64, vp, vp, i32, i32, i32, i32, i32, f64]
+        L.orc_lite_begin.restype = vp
+        L.orc_lite_query.argtypes = [vp, i64, i64, vp, vp, vp, vp]
+        L.orc_lite_end.argtypes = [vp]
+        L.orc_lite_end.restype = None
+        L.orc_stages.argtypes = [i64, vp, vp, i32, i32, i32, f64, f64, f64, i32, vp, vp, vp, vp,
+                                 vp, vp, vp, vp, vp, vp]
         L.orc_num_threads.restype = i32
         _LIB = L
     return _LIB
@@ -214,3 +225,123 @@ def run(pos, periodic=True, mean_density=None, params: HopParams | None = None, 
     g = int(counts[2])
     return OracleResult(dens, nbr, hop_, root, chain_of, group, gc[:g].copy(), gp[:g].copy(),
                         gd[:g].copy(), int(counts[0]), int(counts[1]), g)
+
+
+@dataclass
+class LiteResult:
+    density: np.ndarray
+    nbr: np.ndarray        # [n][k_keep] list heads
+    row_hash: np.ndarray   # [n] uint64 fingerprint of the first k_store entries
+    r2max: np.ndarray      # [n] d^2 to the N_dens-th entry
+    hop: np.ndarray
+    root: np.ndarray
+    chain_of: np.ndarray
+    group: np.ndarray
+    g_count: np.ndarray
+    g_peak: np.ndarray
+    g_peak_dens: np.ndarray
+    n_chains: int
+    n_edges: int
+    n_groups: int
+
+
+def run_lite(pos, periodic=True, mean_density=None, params: HopParams | None = None, ids=None,
+             padded=None, padded_rules=False, k_keep=16, chunk=1 << 20) -> LiteResult:
+    """orc_run in bounded memory: list heads, row fingerprints, all other outputs."""
+    p = params or HopParams()
+    pos = _c(pos, np.uint32)
+    n = pos.shape[0]
+    if mean_density is None:
+        mean_density = n / float(1 << (3 * p.grid_bits))
+    dens = np.empty(n, np.float64)
+    nbr = np.empty((n, k_keep), np.int32)
+    rh = np.empty(n, np.uint64)
+    r2 = np.empty(n, np.int64)
+    hop_ = np.empty(n, np.int32)
+    root = np.empty(n, np.int32)
+    chain_of = np.empty(n, np.int32)
+    group = np.empty(n, np.int32)
+    gc = np.empty(max(n, 1), np.int64)
+    gp = np.empty(max(n, 1), np.int32)
+    gd = np.empty(max(n, 1), np.float64)
+    counts = np.zeros(3, np.int64)
+    _check(lib().orc_run_lite(n, _p(pos), _p(_c(ids, np.int64)), _p(_c(padded, np.uint8)),
+                              int(periodic), p.grid_bits, p.n_dens, p.n_hop, p.n_merge,
+                              p.k_store, int(k_keep), p.delta_outer, p.delta_saddle,
+                              p.delta_peak, float(mean_density), int(padded_rules), int(chunk),
+                              _p(dens), _p(nbr), _p(rh), _p(r2), _p(hop_), _p(root),
+                              _p(chain_of), _p(group), _p(gc), _p(gp), _p(gd), _p(counts)),
+           "run_lite")
+    g = int(counts[2])
+    return LiteResult(dens, nbr, rh, r2, hop_, root, chain_of, group, gc[:g].copy(),
+                      gp[:g].copy(), gd[:g].copy(), int(counts[0]), int(counts[1]), g)
+
+
+def stages(nbr, dens, params: HopParams | None = None, ids=None, padded=None,
+           padded_rules=False):
+    """Stages 3-7 (links, chains, boundaries, merge, labels) from densities and
+    the first list columns; returns (hop, root, chain_of, group, g_count,
+    g_peak, g_peak_dens, n_chains, n_edges, n_groups)."""
+    p = params or HopParams()
+    nbr = _c(nbr, np.int32)
+    n, kc = nbr.shape
+    hop_ = np.empty(n, np.int32)
+    root = np.empty(n, np.int32)
+    chain_of = np.empty(n, np.int32)
+    group = np.empty(n, np.int32)
+    gc = np.empty(max(n, 1), np.int64)
+    gp = np.empty(max(n, 1), np.int32)
+    gd = np.empty(max(n, 1), np.float64)
+    counts = np.zeros(3, np.int64)
+    _check(lib().orc_stages(n, _p(_c(ids, np.int64)), _p(_c(padded, np.uint8)), p.n_hop,
+                            p.n_merge, kc, p.delta_outer, p.delta_saddle, p.delta_peak,
+                            int(padded_rules), _p(_c(dens, np.float64)), _p(nbr), _p(hop_),
+                            _p(root), _p(chain_of), _p(group), _p(gc), _p(gp), _p(gd),
+                            _p(counts)), "stages")
+    g = int(counts[2])
+    return (hop_, root, chain_of, group, gc[:g].copy(), gp[:g].copy(), gd[:g].copy(),
+            int(counts[0]), int(counts[1]), g)
+
+
+class Lite:
+    """Incremental bounded-memory pipeline: the kd-tree is built on creation,
+    query(c0, c1) searches the particles at tree positions [c0, c1), and
+    finish() runs the later stages.  Outputs fill the arrays held here."""
+
+    def __init__(self, pos, periodic=True, mean_density=None, params: HopParams | None = None,
+                 ids=None, k_keep=16):
+        self.p = params or HopParams()
+        self.pos = _c(pos, np.uint32)
+        self.ids = _c(ids, np.int64)
+        self.n = n = self.pos.shape[0]
+        if mean_density is None:
+            mean_density = n / float(1 << (3 * self.p.grid_bits))
+        self.density = np.empty(n, np.float64)
+        self.nbr = np.empty((n, k_keep), np.int32)
+        self.row_hash = np.empty(n, np.uint64)
+        self.r2max = np.empty(n, np.int64)
+        self.h = lib().orc_lite_begin(n, _p(self.pos), _p(self.ids), int(periodic),
+                                      self.p.grid_bits, self.p.n_dens, self.p.k_store,
+                                      int(k_keep), float(mean_density))
+        if not self.h:
+            raise RuntimeError("oracle lite_begin failed")
+
+    def query(self, c0, c1):
+        _check(lib().orc_lite_query(self.h, int(c0), int(c1), _p(self.density), _p(self.nbr),
+                                    _p(self.row_hash), _p(self.r2max)), "lite_query")
+
+    def close(self):
+        if self.h:
+            lib().orc_lite_end(self.h)
+            self.h = None
+
+    def finish(self, padded=None, padded_rules=False):
+        self.close()
+        return stages(self.nbr, self.density, self.p, ids=self.ids, padded=padded,
+                      padded_rules=padded_rules)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
