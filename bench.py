@@ -32,16 +32,20 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per particle of the kNN + density kernel:
-# read the sorted position (12) and its index (4); write 64 neighbour
-# indices (256) and the density (8); in the fused density + link call
-# (the box workload) it also writes the Morton-order copy of the first 16
-# indices and the density (72) that the link kernel reads
+# algorithmic HBM bytes per particle of the kNN + density kernel (what the
+# method must move): read the sorted position (12) and its tie key (4);
+# write 64 neighbour indices (256) and the density (8)
 KNN_BYTES_PER_PARTICLE = 12 + 4 + 4 * 64 + 8
+# written besides by this library's fused density + link call (its own
+# layout, not the method's work): the Morton-order copy of the first 16
+# indices and the density (72) that the link kernel reads
 KNN_COPY_BYTES_PER_PARTICLE = 4 * 16 + 8
-# whole path (all stages), bytes per particle, same accounting; the fused
-# call adds the copy and each particle's index read back by the link (76)
+# whole path (all stages), bytes per particle, same accounting
 PATH_BYTES_PER_PARTICLE = 438
+# VALU peak: 256 compute units x 4 SIMDs x 16 lanes x 2.4 GHz, one lane
+# operation per lane and cycle (a wave64 VALU instruction occupies a SIMD
+# for 4 cycles)
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
 def log(msg):
@@ -57,6 +61,9 @@ KNN_SOURCES = [os.path.join(ROOT, "paper_1001_3411_amd", "csrc", f)
                for f in ("hop_knn.hip", "hop_internal.h")]
 
 
+VALU_FILE = os.path.join(ROOT, "profiles", "knn_valu_nfw134m.txt")
+
+
 def knn_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -66,20 +73,46 @@ def knn_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """Bytes per kNN launch from the counter summary, or None."""
+def _summary(path):
+    """key: value lines of a counter summary, or None when the kernel sources
+    no longer hash to the ones it was measured on."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             for line in f:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
-        if kv.get("source_hash") != knn_source_hash():
-            return None
-        return float(kv["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+        return kv if kv.get("source_hash") == knn_source_hash() else None
+    except OSError:
         return None
+
+
+def measured_traffic():
+    """Bytes per kNN launch from the counter summary, or None."""
+    kv = _summary(TRAFFIC_FILE)
+    try:
+        return None if kv is None else float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_valu(n, knn_ms):
+    """VALU use of the kNN kernel from the counter summary, or None."""
+    kv = _summary(VALU_FILE)
+    if kv is None:
+        return None
+    try:
+        insts = float(kv["SQ_INSTS_VALU_per_launch"])
+        busy = float(kv["valu_busy"])
+    except (KeyError, ValueError):
+        return None
+    buckets = (n + 63) // 64
+    achieved = insts * 64 / (knn_ms / 1e3)
+    return {"insts_per_bucket": round(insts / buckets, 1),
+            "achieved_lane_ops": achieved, "peak_lane_ops": VALU_PEAK_LANE_OPS,
+            "frac": round(achieved / VALU_PEAK_LANE_OPS, 4), "valu_busy": busy,
+            "source": os.path.relpath(VALU_FILE, ROOT)}
 
 
 def copy_probe():
@@ -95,38 +128,70 @@ def copy_probe():
     del src, dst
 
 
+def _oracle_rate(pos, mean_density, periodic, threads=None):
+    import oracle
+    before = oracle.num_threads()
+    if threads is not None:
+        oracle.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        r = oracle.run(pos, periodic=periodic, mean_density=mean_density)
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(before)
+    return pos.shape[0] / dt, dt, r.n_groups
+
+
 def cpu_baseline(p, budget_frac=4):
     """The CPU oracle on a bounded sample of the same workload: the particles
     of one sub-cube of side 1/budget_frac of the box, as a non-periodic
-    subvolume, normalised by the whole box's mean density."""
+    subvolume, normalised by the whole box's mean density; then one thread
+    on the 32,768-particle box and on a smaller sub-cube (the per-core rate
+    to set beside the paper's)."""
     import numpy as np
     import oracle
+    import synth
+    threads = oracle.num_threads()
     side = (1 << 21) // budget_frac
-    sel = np.all(p.pos < side, axis=1)
-    sub = np.ascontiguousarray(p.pos[sel])
-    t0 = time.perf_counter()
-    r = oracle.run(sub, periodic=False, mean_density=p.mean_density)
-    dt = time.perf_counter() - t0
-    return {"value": sub.shape[0] / dt, "unit": "particles/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{sub.shape[0]} particles in the [0, 1/{budget_frac})^3 sub-cube of the "
-                      f"same box, whole pipeline (kd-tree kNN, density, links, chains, "
-                      f"boundaries, merge, labels), {dt:.1f} s, {r.n_groups} groups"}
+    sub = np.ascontiguousarray(p.pos[np.all(p.pos < side, axis=1)])
+    rate, dt, ng = _oracle_rate(sub, p.mean_density, False)
+    out = {"value": rate, "unit": "particles/s", "cores": threads, "kind": "oracle",
+           "sample": f"{sub.shape[0]} particles in the [0, 1/{budget_frac})^3 sub-cube of the "
+                     f"same box, whole pipeline (kd-tree kNN, density, links, chains, "
+                     f"boundaries, merge, labels), {dt:.1f} s, {ng} groups"}
+    one = []
+    p1 = synth.config(1)
+    r1, d1, _ = _oracle_rate(p1.pos, p1.mean_density, True, threads=1)
+    one.append({"value": r1, "sample": f"{p1.name} whole box, {d1:.1f} s"})
+    side8 = (1 << 21) // 8
+    sub8 = np.ascontiguousarray(p.pos[np.all(p.pos < side8, axis=1)])
+    r8, d8, _ = _oracle_rate(sub8, p.mean_density, False, threads=1)
+    one.append({"value": r8, "sample": f"{sub8.shape[0]} particles in the [0, 1/8)^3 sub-cube "
+                                       f"of the same box, {d8:.1f} s"})
+    out["one_thread"] = one
+    return out
 
 
 def knn_roofline(n, knn_ms, kernel, value, fused=False):
+    """HBM roofline of the kNN kernel on the method's bytes (280 per
+    particle); the fused call's Morton-order copy is reported apart as
+    overhead.  The kernel is bound by its VALU work, reported in "valu"."""
     knn_s = knn_ms / 1e3
-    per = KNN_BYTES_PER_PARTICLE + (KNN_COPY_BYTES_PER_PARTICLE if fused else 0)
-    path = PATH_BYTES_PER_PARTICLE + (KNN_COPY_BYTES_PER_PARTICLE + 4 if fused else 0)
+    per = KNN_BYTES_PER_PARTICLE
+    over = KNN_COPY_BYTES_PER_PARTICLE if fused else 0
     achieved = per * n / knn_s / 1e9
-    # counter-measured bytes per launch hold for the 134M box's kernel only
-    traffic = measured_traffic() if (kernel == "k_knn_density" and n == 134217728) else None
+    # counter-measured figures hold for the 134M box's kernel only
+    box = kernel == "k_knn_density" and n == 134217728
+    traffic = measured_traffic() if box else None
     return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
             "traffic": traffic, "traffic_gbs": None if traffic is None else round(traffic / knn_s / 1e9, 2),
             "kernel_ms": round(knn_ms, 3),
             "bytes_per_particle": per,
-            "path_frac": round(path * value / 1e9 / HBM_PEAK_GBS, 5)}
+            "overhead_bytes_per_particle": over,
+            "frac_with_overhead": round((per + over) * n / knn_s / 1e9 / HBM_PEAK_GBS, 5),
+            "path_frac": round(PATH_BYTES_PER_PARTICLE * value / 1e9 / HBM_PEAK_GBS, 5),
+            "valu": measured_valu(n, knn_ms) if box else None}
 
 
 def radius_models(ctx, log_fn):
@@ -274,9 +339,21 @@ def bench_box(args):
     if not args.no_cpu:
         try:
             cpu = cpu_baseline(p)
-            log(f"cpu baseline: {cpu['value']:.3g} particles/s on {cpu['cores']} threads")
+            log(f"cpu baseline: {cpu['value']:.3g} particles/s on {cpu['cores']} threads; "
+                f"one thread: {[round(o['value']) for o in cpu['one_thread']]}")
         except Exception as e:  # the baseline is reported, never required
             log(f"cpu baseline failed: {e}")
+    batch = None
+    if args.batch:
+        # the batched form on the same GPU: the 64-subvolume workload, one
+        # batched call against 64 sequential calls, identical outputs
+        ctx.close()
+        del pos
+        torch.cuda.empty_cache()
+        b = bench_batch(args, cpu=False)
+        batch = {k: b[k] for k in ("value", "ms_per_step", "sequential", "speedup_vs_sequential",
+                                   "config")}
+        batch["kernel_ms"] = b["roofline"]["kernel_ms"]
     return {"metric": "HOP particles/sec at 134M clustered (plain vs learned-radius); % HBM roofline",
             "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
@@ -285,10 +362,10 @@ def bench_box(args):
                        "n_merge": prm.n_merge, "k_store": prm.k_store, "periodic": p.periodic,
                        "search": "plain", "groups": groups, "chains": chains},
             "roofline": roofline, "halo_stats": halo,
-            "cpu_baseline": cpu, "search_compare": search}
+            "cpu_baseline": cpu, "search_compare": search, "batch64": batch}
 
 
-def bench_batch(args):
+def bench_batch(args, cpu=True):
     import numpy as np
     import torch
 
@@ -361,8 +438,8 @@ def bench_batch(args):
     value = n / (dt / args.steps)
     log(f"{args.steps} steps: batched {ms_step:.2f} ms/step (kNN {np.mean(knn_ms):.2f} ms), "
         f"sequential {ms_seq:.2f} ms/step")
-    cpu = None
-    if not args.no_cpu:
+    cpu_line = None
+    if cpu and not args.no_cpu:
         try:
             import oracle
             k, t_cpu, done = 0, 0.0, 0
@@ -374,7 +451,7 @@ def bench_batch(args):
                 t_cpu += time.perf_counter() - t2
                 done += q.n
                 k += 1
-            cpu = {"value": done / t_cpu, "unit": "particles/s", "cores": oracle.num_threads(),
+            cpu_line = {"value": done / t_cpu, "unit": "particles/s", "cores": oracle.num_threads(),
                    "kind": "oracle",
                    "sample": f"the first {k} subvolumes ({done} particles), whole pipeline "
                              f"each, {t_cpu:.1f} s"}
@@ -391,7 +468,7 @@ def bench_batch(args):
                            "launches": "64 x (hop_density_link, hop_groups, hop_merge)"},
             "speedup_vs_sequential": ms_seq / ms_step,
             "roofline": knn_roofline(n, float(np.mean(knn_ms)), "k_knn_batch", value),
-            "cpu_baseline": cpu}
+            "cpu_baseline": cpu_line}
 
 
 def main():
@@ -404,6 +481,8 @@ def main():
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--search", choices=["compare", "plain"], default="compare")
+    ap.add_argument("--no-batch", dest="batch", action="store_false",
+                    help="box workload: skip the batched-vs-sequential comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference for the traffic counters)")
     args = ap.parse_args()

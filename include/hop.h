@@ -12,7 +12,7 @@
  *   hop_merge    boundary table, proto-halo and sub-peak merge,
  *                group labels                                        (sec. 2, merge steps 2-5;
  *                                                                     sec. 3.1 last step)
- *   hop_stitch   whole-box density and lists from padded subvolumes (sec. 3.1)
+ *   hop_stitch   whole-box chains and halos from padded subvolumes   (sec. 3.1)
  *   hop_halo_stats  per-halo count, centre, maximum radius, bulk velocity
  *                (sec. 3.1 output step)
  *
@@ -200,6 +200,9 @@ int hop_density_link(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
  * root      [n] output
  * chain_of  [n] output
  * n_chains  HOST pointer, output.  Synchronises `stream`.
+ * Errors: HOP_ERR_RANGE when a link is outside [0, n); HOP_ERR_ARG when
+ * the links close a cycle, so that some particle reaches no self-linked
+ * particle (links from hop_link always go uphill and never do).
  */
 int hop_groups(hop_ctx *ctx, int64_t n, const int32_t *hop, const double *density,
                const int64_t *id, const hop_params *p, int32_t *root, int32_t *chain_of,
@@ -237,31 +240,52 @@ int hop_merge(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density
               hop_group_info *groups, void *stream);
 
 /*
- * hop_stitch -- whole-box density and neighbour lists from padded
- * subvolumes (section 3.1: each task's local particles, given enough
- * padding, have their whole-box neighbours and density; the tasks' results
- * are then joined).  On one GPU the join is a scatter: every row of the
- * batched call that is not padding writes its density and its list,
- * mapped from subvolume rows to box indices, at its box index; the box's
- * links, chains, boundaries and groups then come from hop_link, hop_groups
- * and hop_merge on these arrays.  With every local particle's neighbour
- * sphere inside its padded subvolume, and each subvolume's rows in
- * increasing box index (so ties go the same way), the result equals the
- * whole-box run.
+ * hop_stitch -- whole-box chains and halos from padded subvolumes (section
+ * 3.1: after each task's own densities and links, chains broken at a
+ * subvolume's edge are rebuilt through the padded particles they end on,
+ * padded particles take their owners' chains, one boundary table gathers
+ * every task's chain pairs, and the merge and labels run once for the box;
+ * optionally, each task first premerges its own proto-halos).
+ *
+ * Input: the rows of hop_run_batch over padded subvolumes cut from one box
+ * (with HOP_PADDED_RULES: padded rows link to themselves), each row's box
+ * index, and its padding flag.  A chain of a subvolume that ends on a padded
+ * row continues at that particle's row in the subvolume where it is local
+ * (its owner): following links and these owner steps reaches a local,
+ * self-linked row, the chain's peak.  Chains are the peaks at or above
+ * delta_outer, numbered by box index.  Every row takes the chain of its
+ * owner; boundaries come from every row and its n_merge - 1 listed
+ * neighbours (not both padded), with the rows' own densities; merge and
+ * labels then follow hop_merge, counting local rows only.  With premerge,
+ * each subvolume first joins its own chains (peaks as that subvolume sees
+ * them) that reach delta_peak and share a boundary >= delta_saddle; the
+ * final merge keeps those joins.  When every local particle's neighbours
+ * and their densities are the whole-box ones (enough padding, rows of each
+ * subvolume in increasing box index so that ties go the same way), the
+ * outputs equal those of the whole-box run.
  *
  * offsets    HOST [n_sub + 1] row ranges of the batch, offsets[0] = 0
- * index      [rows] int64: the box index of each batch row
- * padded     [rows] uint8 or NULL (nonzero rows are skipped)
- * density_b  [rows], nbr_b [rows][k_store]: hop_run_batch outputs (rows
- *            local to their subvolume)
- * density    [n] output; nbr [n][k_store] output or NULL
- * Every box index must be the core row of exactly one subvolume (else its
- * outputs are not written).  Synchronises `stream`; a box index or list
- * entry out of range is HOP_ERR_RANGE.
+ * index      [rows] int64: the box index of each row
+ * padded     [rows] uint8 (nonzero = padding row); required
+ * density_b, nbr_b [rows][k_store], hop_b   hop_run_batch outputs (local
+ *            to each subvolume)
+ * p          the box's parameters (HOP_PADDED_RULES required; k_store is
+ *            nbr_b's row length)
+ * premerge   nonzero: the premerge step above
+ * n          box particles; every box index must be the local row of
+ *            exactly one subvolume (else HOP_ERR_ARG)
+ * density, hop (or NULL), root, chain_of, group   [n] box outputs, box
+ *            indices
+ * n_chains, n_groups   HOST outputs
+ * groups     [rows] device group table or NULL (peaks are box indices)
+ * Synchronises `stream`; a row index or link outside its subvolume is
+ * HOP_ERR_RANGE.
  */
 int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, const int64_t *index,
                const uint8_t *padded, const double *density_b, const int32_t *nbr_b,
-               int32_t k_store, int64_t n, double *density, int32_t *nbr, void *stream);
+               const int32_t *hop_b, const hop_params *p, int32_t premerge, int64_t n,
+               double *density, int32_t *hop, int32_t *root, int32_t *chain_of, int32_t *group,
+               int32_t *n_chains, int32_t *n_groups, hop_group_info *groups, void *stream);
 
 /*
  * hop_halo_stats -- per-halo statistics (section 3.1, the output step: each
@@ -287,8 +311,10 @@ int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, const int64_
  * com      [n_groups][3] FP64 output
  * rmax     [n_groups] FP64 output
  * vbulk    [n_groups][3] FP64 output, or NULL when vel is NULL
- * Errors: HOP_ERR_ARG for bad sizes or NULL outputs; a group number or
- * peak outside range is reported by the next synchronising call.
+ * Synchronises `stream`.
+ * Errors: HOP_ERR_ARG for bad sizes or NULL outputs; HOP_ERR_RANGE when a
+ * group number or a table peak is outside range (that group's outputs are
+ * not written; nothing is read at the bad index).
  */
 int hop_halo_stats(hop_ctx *ctx, int64_t n, const uint32_t *pos, const float *vel,
                    const int32_t *group, int32_t n_groups, const hop_group_info *groups,
@@ -341,12 +367,17 @@ int hop_run_batch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, const uin
  *                   move on to the other chunks (default); 0 = one queue
  * largest_first     batched launch: 1 = subvolumes in decreasing size
  *                   (default); 0 = in the given order
+ * hash_slots        initial slots of the boundary table, rounded up to a
+ *                   power of two (0 = sized from the chain and pair counts,
+ *                   default; 1..2^30 otherwise).  A table that overflows is
+ *                   doubled and rebuilt until it holds every chain pair.
  */
 typedef struct hop_tuning {
     int32_t front_cap;
     int32_t persistent_waves;
     int32_t xcd_queues;
     int32_t largest_first;
+    int32_t hash_slots;
 } hop_tuning;
 
 int hop_set_tuning(hop_ctx *ctx, const hop_tuning *t);
@@ -424,7 +455,8 @@ int hop_radius_predict(hop_ctx *ctx, int64_t rows, const float *feats, int32_t n
    last synchronising call (see the conventions above). */
 int hop_sync(hop_ctx *ctx, void *stream);
 
-/* Per-call statistics of the last hop_density on this context. */
+/* Per-call statistics of the last hop_density (and premerge count of the
+   last hop_stitch) on this context. */
 typedef struct hop_stats {
     double ms_sort;         /* Morton sort + tree build                          */
     double ms_knn;          /* kNN + density kernel(s), fallback pass included   */
@@ -434,6 +466,8 @@ typedef struct hop_stats {
     double ms_radius;       /* HOP_LEARNED_RADIUS: cell counts + per-cell model  */
     int64_t misses;         /* HOP_LEARNED_RADIUS: particles searched again      */
     int64_t redo_buckets;   /* HOP_LEARNED_RADIUS: buckets of the fallback pass  */
+    int64_t premerged;      /* hop_stitch with premerge: row pairs that joined
+                               two chains inside a subvolume                     */
 } hop_stats;
 
 /* Profiling bits (default 0): 1 = time the sort/tree and kNN stages of

@@ -1014,6 +1014,16 @@ int orc_run_lite(int64_t n, const uint32_t *pos, const int64_t *id, const uint8_
                       g_peak, g_peak_dens, counts);
 }
 
+/* threads of the OpenMP loops from now on (n >= 1) */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -17,7 +17,7 @@ from . import build as _build
 __all__ = [
     "lib", "knn", "density", "norm", "hop", "chains", "saddles", "merge", "labels",
     "run", "run_lite", "Lite", "stages", "OracleResult", "LiteResult", "num_threads",
-    "HopParams",
+    "set_threads", "HopParams",
 ]
 
 _LIB = None
@@ -54,6 +54,8 @@ def lib():
         L.orc_stages.argtypes = [i64, vp, vp, i32, i32, i32, f64, f64, f64, i32, vp, vp, vp, vp,
                                  vp, vp, vp, vp, vp, vp]
         L.orc_num_threads.restype = i32
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_set_threads.restype = None
         _LIB = L
     return _LIB
 
@@ -73,6 +75,11 @@ def _check(rc, what):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    lib().orc_set_threads(int(n))
 
 
 @dataclass

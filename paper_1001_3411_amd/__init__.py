@@ -53,7 +53,8 @@ class _GroupInfo(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [("ms_sort", C.c_double), ("ms_knn", C.c_double), ("n", C.c_int64),
                 ("nodes_visited", C.c_int64), ("leaves_scanned", C.c_int64),
-                ("ms_radius", C.c_double), ("misses", C.c_int64), ("redo_buckets", C.c_int64)]
+                ("ms_radius", C.c_double), ("misses", C.c_int64), ("redo_buckets", C.c_int64),
+                ("premerged", C.c_int64)]
 
 
 @dataclass
@@ -86,7 +87,8 @@ class HopParams:
 
 class _Tuning(C.Structure):
     _fields_ = [("front_cap", C.c_int32), ("persistent_waves", C.c_int32),
-                ("xcd_queues", C.c_int32), ("largest_first", C.c_int32)]
+                ("xcd_queues", C.c_int32), ("largest_first", C.c_int32),
+                ("hash_slots", C.c_int32)]
 
 
 _LIB = None
@@ -116,7 +118,8 @@ def load():
     L.hop_merge.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, C.POINTER(_Params), vp,
                             C.POINTER(i32), vp, vp]
     L.hop_halo_stats.argtypes = [vp, i64, vp, vp, vp, i32, vp, C.POINTER(_Params), vp, vp, vp, vp]
-    L.hop_stitch.argtypes = [vp, i32, vp, vp, vp, vp, vp, i32, i64, vp, vp, vp]
+    L.hop_stitch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(_Params), i32, i64, vp,
+                             vp, vp, vp, vp, C.POINTER(i32), C.POINTER(i32), vp, vp]
     L.hop_run_batch.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(_Params), vp, vp, vp, vp, vp,
                                 vp, vp, vp, vp, vp, vp]
     f32 = C.c_float
@@ -282,21 +285,37 @@ class HopContext:
             out["g_peak_dens"] = t[:, 2].contiguous().view(torch.float64)
         return out
 
-    def stitch(self, offsets, index, padded, density_b, nbr_b, n, k_store=64, stream=None):
-        """hop_stitch: box density [n] and lists [n][k_store] from the batched
-        call's rows (offsets host, index/padded per row)."""
+    def stitch(self, offsets, index, padded, batch, n, params: HopParams | None = None,
+               premerge=False, stream=None):
+        """hop_stitch: whole-box chains and halos from the rows of a batched
+        run (batch = run_batch() output; offsets host, index/padded per row).
+        Returns device box arrays and the group table."""
         import numpy as np
         torch = self._torch
+        p = params or HopParams()
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         idx_d = self._dev(index, torch.int64)
         pad_d = self._dev(padded, torch.uint8)
-        dev = density_b.device
-        dens = torch.empty(n, dtype=torch.float64, device=dev)
-        nbr = torch.empty((n, k_store), dtype=torch.int32, device=dev) if nbr_b is not None else None
-        self._check(self.lib.hop_stitch(self.h, off.size - 1, off.ctypes.data_as(C.c_void_p), _ptr(idx_d),
-                                        _ptr(pad_d), _ptr(density_b), _ptr(nbr_b), int(k_store), int(n),
-                                        _ptr(dens), _ptr(nbr), self._stream(stream)))
-        return dens, nbr
+        dev = batch["density"].device
+        out = {k: torch.empty(n, dtype=torch.int32, device=dev)
+               for k in ("hop", "root", "chain_of", "group")}
+        out["density"] = torch.empty(n, dtype=torch.float64, device=dev)
+        table = torch.empty((max(int(off[-1]), 1), 3), dtype=torch.int64, device=dev)
+        nc, ng = C.c_int32(0), C.c_int32(0)
+        cp = p.c()
+        self._check(self.lib.hop_stitch(self.h, off.size - 1, off.ctypes.data_as(C.c_void_p),
+                                        _ptr(idx_d), _ptr(pad_d), _ptr(batch["density"]),
+                                        _ptr(batch["nbr"]), _ptr(batch["hop"]), C.byref(cp),
+                                        int(bool(premerge)), int(n), _ptr(out["density"]),
+                                        _ptr(out["hop"]), _ptr(out["root"]), _ptr(out["chain_of"]),
+                                        _ptr(out["group"]), C.byref(nc), C.byref(ng), _ptr(table),
+                                        self._stream(stream)))
+        g = int(ng.value)
+        t = table[:g]
+        out.update(n_chains=int(nc.value), n_groups=g, table=t, g_count=t[:, 0].clone(),
+                   g_peak=(t[:, 1] & 0xFFFFFFFF).to(torch.int32),
+                   g_peak_dens=t[:, 2].contiguous().view(torch.float64))
+        return out
 
     def halo_stats(self, pos, group, table, params: HopParams | None = None, vel=None,
                    stream=None):
@@ -448,7 +467,7 @@ class HopContext:
 
     def set_tuning(self, **kw):
         """Change launch settings (front_cap, persistent_waves, xcd_queues,
-        largest_first); results never depend on them."""
+        largest_first, hash_slots); results never depend on them."""
         t = _Tuning()
         self._check(self.lib.hop_get_tuning(self.h, C.byref(t)))
         for k, v in kw.items():

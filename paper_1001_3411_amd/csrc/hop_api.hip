@@ -61,15 +61,19 @@ int hop_check_device(hop_ctx *ctx, hipStream_t s, const char *stage)
     HOPCHK(ctx, hipMemsetAsync(dflags, 0, 4, s));
     HOPCHK(ctx, hipStreamSynchronize(s));
     std::string where = std::string(stage) + ": ";
+    // causes first: a list the search could not fill (degenerate or beyond
+    // the key range) also leaves indices that later stages flag
     if (f & DERR_RANGE) return hop_fail(ctx, HOP_ERR_RANGE, where + "a coordinate is >= 2^grid_bits");
-    if (f & DERR_INDEX) return hop_fail(ctx, HOP_ERR_RANGE, where + "an input index is outside [0, n)");
     if (f & DERR_DEGENERATE)
         return hop_fail(ctx, HOP_ERR_DEGENERATE, where + "r_max = 0: n_dens or more coincident particles");
     if (f & DERR_KEYWIDTH)
         return hop_fail(ctx, HOP_ERR_CAPACITY, where + "a neighbour distance exceeds the packed key range");
+    if (f & DERR_INDEX) return hop_fail(ctx, HOP_ERR_RANGE, where + "an input index is outside [0, n)");
     if (f & DERR_CAPACITY) return hop_fail(ctx, HOP_ERR_CAPACITY, where + "an internal table overflowed");
     if (f & DERR_CYCLE) return hop_fail(ctx, HOP_ERR_ARG, where + "links do not reach a self-linked particle");
     if (f & DERR_IDS) return hop_fail(ctx, HOP_ERR_ARG, where + "ids are not distinct");
+    if (f & DERR_OWNER)
+        return hop_fail(ctx, HOP_ERR_ARG, where + "a box index is not the core row of exactly one subvolume");
     return hop_fail(ctx, HOP_ERR_HIP, where + "unknown device error");
 }
 
@@ -77,8 +81,8 @@ int hop_check_params(hop_ctx *ctx, int64_t n, const hop_params *p)
 {
     if (!p) return hop_fail(ctx, HOP_ERR_ARG, "params is NULL");
     if (!(1 <= p->n_merge && p->n_merge <= p->n_hop && p->n_hop <= p->k_store &&
-          p->k_store <= p->n_dens && p->n_dens <= 64 && p->n_dens >= 2))
-        return hop_fail(ctx, HOP_ERR_ARG, "need 1 <= n_merge <= n_hop <= k_store <= n_dens <= 64, n_dens >= 2");
+          p->k_store <= p->n_dens && p->n_dens <= 128 && p->n_dens >= 2))
+        return hop_fail(ctx, HOP_ERR_ARG, "need 1 <= n_merge <= n_hop <= k_store <= n_dens <= 128, n_dens >= 2");
     if (p->grid_bits < 1 || p->grid_bits > 21) return hop_fail(ctx, HOP_ERR_ARG, "grid_bits must be in [1, 21]");
     const double d[3] = {p->delta_outer, p->delta_saddle, p->delta_peak};
     for (double v : d)
@@ -158,7 +162,7 @@ void hop_ctx_destroy(hop_ctx *ctx)
                       &ctx->work_f, &ctx->hash_keys, &ctx->hash_vals, &ctx->edges_lo,
                       &ctx->edges_hi, &ctx->edges_s, &ctx->batch_tab, &ctx->batch_aux,
                       &ctx->cell_counts, &ctx->cell_r, &ctx->radius_w, &ctx->mlp_part, &ctx->miss,
-                      &ctx->srt_nbr, &ctx->srt_dens, &ctx->jump_done};
+                      &ctx->srt_nbr, &ctx->srt_dens, &ctx->jump_done, &ctx->stitch};
     for (DevBuf *b : bufs)
         if (b->ptr) hipFree(b->ptr);
     if (ctx->hflags) hipHostFree(ctx->hflags);
@@ -187,6 +191,8 @@ int hop_set_tuning(hop_ctx *ctx, const hop_tuning *t)
         return hop_fail(ctx, HOP_ERR_ARG, "persistent_waves must be in [0, 2^20]");
     if ((t->xcd_queues != 0 && t->xcd_queues != 1) || (t->largest_first != 0 && t->largest_first != 1))
         return hop_fail(ctx, HOP_ERR_ARG, "xcd_queues and largest_first must be 0 or 1");
+    if (t->hash_slots < 0 || t->hash_slots > (1 << 30))
+        return hop_fail(ctx, HOP_ERR_ARG, "hash_slots must be in [0, 2^30]");
     ctx->tuning = *t;
     return HOP_OK;
 }
@@ -307,7 +313,7 @@ int hop_merge(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density
         tk = (const int32_t *)ctx->tk.ptr;
     }
     return hop_merge_impl(ctx, n, nbr, density, root, chain_of, n_chains, tk, padded, p, group,
-                          n_groups, groups, nullptr, 0, nullptr, s);
+                          n_groups, groups, MergeExtra{}, s);
 }
 
 }  // extern "C"

@@ -150,8 +150,12 @@ extern "C" int hop_run_batch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets
     std::vector<int32_t> gf(n_sub + 1, 0);
     HOPCHK(ctx, hipMemsetAsync(gfirst, 0xff, (size_t)(n_sub + 1) * 4, s));
     int32_t ng = 0;
+    MergeExtra mx;
+    mx.chain_base = nc > 0 ? cbase : nullptr;
+    mx.n_sub = n_sub;
+    mx.group_first = gfirst;
     HOPTRY(hop_merge_impl(ctx, n, nbr, density, root, chain_of, nc, nullptr, padded, p, group, &ng,
-                          groups, nc > 0 ? cbase : nullptr, n_sub, gfirst, s));
+                          groups, mx, s));
     std::vector<int32_t> cb(n_sub + 1, 0);
     if (nc > 0) {
         HOPCHK(ctx, hipMemcpyAsync(cb.data(), cbase, (size_t)(n_sub + 1) * 4, hipMemcpyDeviceToHost, s));
@@ -184,63 +188,3 @@ extern "C" int hop_run_batch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets
     return HOP_OK;
 }
 
-namespace {
-
-// one batch row: a core row writes its density and its neighbour list,
-// mapped from subvolume rows to box indices, at its box index
-__global__ void k_stitch(int64_t rows, const int64_t *__restrict__ off, int n_sub,
-                         const int64_t *__restrict__ index, const uint8_t *__restrict__ padded,
-                         const double *__restrict__ density_b, const int32_t *__restrict__ nbr_b,
-                         int k_store, int64_t n, double *__restrict__ density,
-                         int32_t *__restrict__ nbr, uint32_t *__restrict__ dflags)
-{
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= rows) return;
-    if (padded && padded[r]) return;
-    const int sv = sub_of(off, n_sub, r);
-    const int64_t base = off[sv], cnt = off[sv + 1] - base;
-    const int64_t g = index[r];
-    if (g < 0 || g >= n) {
-        atomicOr(dflags, DERR_INDEX);
-        return;
-    }
-    density[g] = density_b[r];
-    if (!nbr) return;
-    for (int t = 0; t < k_store; t++) {
-        const int32_t j = nbr_b[r * k_store + t];
-        int32_t J = -1;
-        if (j >= 0 && j < cnt) J = (int32_t)index[base + j];
-        else atomicOr(dflags, DERR_INDEX);
-        nbr[g * k_store + t] = J;
-    }
-}
-
-}  // namespace
-
-extern "C" int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, const int64_t *index,
-                          const uint8_t *padded, const double *density_b, const int32_t *nbr_b,
-                          int32_t k_store, int64_t n, double *density, int32_t *nbr, void *stream)
-{
-    if (!ctx) return HOP_ERR_ARG;
-    ctx->err.clear();
-    if (n_sub < 1 || n_sub > 65536 || !offsets || offsets[0] != 0)
-        return hop_fail(ctx, HOP_ERR_ARG, "need 1 <= n_sub <= 65536 and offsets from 0");
-    if (n < 1 || n >= ((int64_t)1 << 31)) return hop_fail(ctx, HOP_ERR_ARG, "need 1 <= n < 2^31");
-    if (!index || !density_b || !density || (nbr && (!nbr_b || k_store < 1 || k_store > 64)))
-        return hop_fail(ctx, HOP_ERR_ARG, "index, densities and (with nbr) nbr_b, 1 <= k_store <= 64 needed");
-    for (int k = 0; k < n_sub; k++)
-        if (offsets[k + 1] < offsets[k]) return hop_fail(ctx, HOP_ERR_ARG, "offsets must not decrease");
-    const int64_t rows = offsets[n_sub];
-    HOPTRY(hop_set_device(ctx));
-    hipStream_t s = (hipStream_t)stream;
-    HOPTRY(hop_reserve(ctx, ctx->batch_aux, (size_t)(n_sub + 1) * 8));
-    int64_t *off = (int64_t *)ctx->batch_aux.ptr;
-    HOPCHK(ctx, hipMemcpyAsync(off, offsets, (size_t)(n_sub + 1) * 8, hipMemcpyHostToDevice, s));
-    if (rows > 0) {
-        k_stitch<<<hop_grid(rows, 256), 256, 0, s>>>(rows, off, n_sub, index, padded, density_b, nbr_b,
-                                                     k_store, n, density, nbr, (uint32_t *)ctx->flags.ptr);
-        HOPCHK(ctx, hipGetLastError());
-    }
-    // also keeps the host offsets alive until the copy has run
-    return hop_check_device(ctx, s, "hop_stitch");
-}

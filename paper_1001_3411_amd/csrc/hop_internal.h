@@ -18,6 +18,7 @@ enum : uint32_t {
     DERR_CAPACITY = 16u,   // a hash table or queue overflowed
     DERR_CYCLE = 32u,      // links that do not reach a self-linked particle
     DERR_IDS = 64u,        // duplicate ids
+    DERR_OWNER = 128u,     // stitching: a box index is not the core row of exactly one subvolume
 };
 
 // One particle of the Morton-sorted copy: FP64 coordinates (exact copies of
@@ -57,7 +58,7 @@ struct hop_ctx {
     std::string err;
     int profiling = 0;
     int n_cu = 256;  // compute units of the device
-    hop_tuning tuning{1024, 0, 1, 1};
+    hop_tuning tuning{1024, 0, 1, 1, 0};
     hop_stats stats{};
 
     // device scratch
@@ -76,6 +77,7 @@ struct hop_ctx {
     DevBuf miss;                  // learned radius: per-bucket lanes to search again
     DevBuf srt_nbr, srt_dens;     // density + links: sorted copies of list heads and densities
     DevBuf jump_done;             // chains: particles whose root is final
+    DevBuf stitch;                // stitching: owner rows, virtual-link roots, labels
     int radius_kind = 0;          // HOP_RADIUS_* of the loaded model, 0 = none
     float radius_margin = 0.0f;
     float radius_occupancy = 8.0f;
@@ -150,15 +152,30 @@ int hop_link_sorted_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr16s, const d
 int hop_groups_impl(hop_ctx *ctx, int64_t n, const int32_t *hop, const double *density,
                     const int32_t *tk, const hop_params *p, int32_t *root, int32_t *chain_of,
                     int32_t *n_chains, hipStream_t s);
-// chain_base (device, [n_sub+1], or NULL): for a batch, the first chain of
-// each subvolume; the halos are then ordered by subvolume first, and
-// group_first (device, [n_sub]) receives the first group of each
-// subvolume that has one (entries of the others are left alone).
+// Optional inputs of hop_merge_impl beyond the plain call.
+struct MergeExtra {
+    // chain_base (device, [n_sub+1]): for a batch, the first chain of each
+    // subvolume; the halos are then ordered by subvolume first, and
+    // group_first (device, [n_sub]) receives the first group of each
+    // subvolume that has one (entries of the others are left alone)
+    const int32_t *chain_base = nullptr;
+    int32_t n_sub = 0;
+    int32_t *group_first = nullptr;
+    // tk holds the output indices themselves (group peaks are tk values);
+    // otherwise tk is a rank of ids and ctx->tk2j maps it back
+    bool tk_is_index = false;
+    // chain pairs (device, lo[n_pre], hi[n_pre]) joined into one halo before
+    // the labels, besides the proto-halo pairs of the boundary table
+    const int32_t *pre_lo = nullptr, *pre_hi = nullptr;
+    int64_t n_pre = 0;
+};
 int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
                    const int32_t *root, const int32_t *chain_of, int32_t n_chains,
                    const int32_t *tk, const uint8_t *padded, const hop_params *p, int32_t *group,
-                   int32_t *n_groups, hop_group_info *groups, const int32_t *chain_base,
-                   int32_t n_sub, int32_t *group_first, hipStream_t s);
+                   int32_t *n_groups, hop_group_info *groups, const MergeExtra &x, hipStream_t s);
+// Pointer jumping root[i] <- root[root[i]] until no root changes (root
+// holds links on entry, roots on return); HOP_ERR_ARG if it does not end.
+int hop_jump_impl(hop_ctx *ctx, int64_t n, int32_t *root, hipStream_t s);
 // kNN + density for a batch of subvolumes (offsets on the host); neighbour
 // lists hold batch-wide input indices.  *sub_off_dev receives a device copy
 // of the offsets, valid until the next batched call.

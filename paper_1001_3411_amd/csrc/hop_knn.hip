@@ -133,7 +133,8 @@ __global__ void k_level_boxes(NodeBox *__restrict__ boxes, int64_t child_off, in
 // kNN + density
 // ---------------------------------------------------------------------------
 
-constexpr int kHeapMax = 63;   // n_dens - 1 <= 63
+constexpr int kHeapMax = 63;    // n_dens - 1 <= 63 (the default kernels)
+constexpr int kHeapMaxBig = 127; // n_dens - 1 <= 127 (the kernels for n_dens 65..128)
 #ifndef HOP_SEED_SIDES
 #define HOP_SEED_SIDES 1
 #endif
@@ -151,7 +152,12 @@ constexpr int kNearClasses = HOP_NEAR_CLASSES;  // classes streamed before the l
 #endif
 constexpr int kPruneEvery = HOP_PRUNE_EVERY;  // batches between later prunings
 constexpr int kWindow = 32;                    // stream positions per interleave window
-constexpr int kHeapSlots = 65; // 4-ary heap: slots up to 4*15+4 are read
+constexpr int kHeapSlots = 65;     // 4-ary heap of 63: slots up to 4*15+4 are read
+constexpr int kHeapSlotsBig = 130; // 4-ary heap of 127: slots up to 4*31+5 are read
+// LDS heap slots of a kernel instance
+template <bool BIG> constexpr int heap_slots() { return BIG ? kHeapSlotsBig : kHeapSlots; }
+// a sift from slot i reads slots 4i+1 .. 4i+4 while 4i+1 < heap size
+static_assert(kHeapSlots >= kHeapMax + 2 && kHeapSlotsBig >= kHeapMaxBig + 3, "heap slots");
 
 struct KnnArgs {
     const SortedRec *recs;
@@ -302,9 +308,14 @@ __device__ __forceinline__ double d2_wrap(double qx, double qy, double qz, const
     return __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
 }
 
-constexpr int kFrontLevel = 4096;  // frontier entries per level of the breadth-first walk
 constexpr int kLeafList = 1024;    // leaves the walk may hand to the streaming passes
 constexpr int kFront = kLeafList;  // largest frontier_cap honoured
+// Frontier entries per level of the breadth-first walk.  A level that
+// would hold more than kLeafList entries is never used (the walk keeps the
+// previous level), so entries past kLeafList need not be stored; the
+// default kernels have room for more in the heap area they borrow.
+constexpr int kFrontLevel = 4096;
+constexpr int kFrontLevelBig = kLeafList;
 
 // Squared gap between two boxes (minimum image when periodic).
 template <bool PERIODIC>
@@ -353,6 +364,65 @@ __device__ __forceinline__ void lds_sift(uint64_t *heap, int lane, int hs, int i
         i = m;
     }
     heap[i * 64 + lane] = x;
+}
+
+// LDS-only 4-ary sift of x from node i within the first `size` slots
+// (slots from `size` on are ignored: the in-place heapsort keeps its sorted
+// tail there).
+__device__ __forceinline__ void lds_sift_size(uint64_t *heap, int lane, int size, int i, uint64_t x)
+{
+    for (;;) {
+        const int c = 4 * i + 1;
+        if (c >= size) break;
+        uint64_t v = heap[c * 64 + lane];
+        int m = c;
+#pragma unroll
+        for (int q = 1; q < 4; q++) {
+            if (c + q < size) {
+                const uint64_t k = heap[(c + q) * 64 + lane];
+                m = k > v ? c + q : m;
+                v = k > v ? k : v;
+            }
+        }
+        if (v <= x) break;
+        heap[i * 64 + lane] = v;
+        i = m;
+    }
+    heap[i * 64 + lane] = x;
+}
+
+// Pairwise (binary-counter) sum over NSLOT slots of the spline weights of
+// a sorted list: slot 0 is the particle itself (q = 0), slot t < n_dens the
+// list entry whose squared distance d2_at(t - 1) returns, the rest zero.
+// T(a, b) = T(a, m) + T(m, b) over halves, so the order is fixed for any
+// n_dens and adding the zero slots is exact.
+template <int NSLOT, typename F, typename D2At, typename Shape>
+__device__ __forceinline__ F pairwise_spline(int n_dens, F R, D2At d2_at, Shape shape)
+{
+    constexpr int LG = NSLOT == 128 ? 7 : 6;
+    F part[LG + 1];
+#pragma unroll
+    for (int t = 0; t < NSLOT; t++) {
+        F w;
+        if (t == 0) {
+            w = shape((F)0);
+        } else if (t < n_dens) {
+            const uint64_t d2 = d2_at(t - 1);
+            w = shape((F)(4 * d2) / R);
+        } else {
+            w = (F)0;
+        }
+        F sum = w;
+        int lvl = 0;
+#pragma unroll
+        for (int b = 0; b < LG; b++) {
+            if (((t >> b) & 1) == 0) break;
+            sum = part[b] + sum;
+            lvl = b + 1;
+        }
+        part[lvl] = sum;
+    }
+    return part[LG];
 }
 
 // Replace the root by x (x below the root) and restore the heap.  Levels 0
@@ -457,18 +527,22 @@ __device__ __forceinline__ void rh_replace_root(RegHeap &H, uint64_t *heap, int 
 // heap, stage and leaves are the wave's LDS buffers.
 // Only the lanes set in qmask are queries; the others still serve as
 // candidates.
-template <bool PERIODIC, bool IDS>
+// BIG: n_dens up to 128 (heap of up to 127 keys, all but the top two
+// levels in LDS, and the walk's frontier in LDS of its own, `front`);
+// otherwise n_dens up to 64 and the frontier borrows the heap's LDS while
+// the heap's deeper levels are parked in registers (front is unused).
+template <bool PERIODIC, bool IDS, bool BIG>
 __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, const int bcount,
                                            const int64_t plo, const int64_t phi,
                                            const double norm, const float norm32, uint64_t *heap,
-                                           SortedRec *stage, double *stage_pp, uint32_t *leaves,
-                                           const uint64_t qmask,
+                                           uint32_t *front, SortedRec *stage, double *stage_pp,
+                                           uint32_t *leaves, const uint64_t qmask,
                                            const int64_t bucket_id)
 {
-    // the walk's two frontier buffers live in the heap area until the heap
-    // is filled
-    uint32_t *front_a = reinterpret_cast<uint32_t *>(heap);
-    uint32_t *front_b = front_a + kFrontLevel;
+    constexpr int kSlots = heap_slots<BIG>();
+    constexpr int kFL = BIG ? kFrontLevelBig : kFrontLevel;
+    uint32_t *front_a = BIG ? front : reinterpret_cast<uint32_t *>(heap);
+    uint32_t *front_b = front_a + kFL;
 
     const int lane = threadIdx.x;
     const bool active = lane < bcount && ((qmask >> lane) & 1ull);
@@ -500,7 +574,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     //    straight into place, then one heapify) ...
     RegHeap H;
     {
-        for (int s = 0; s < kHeapSlots; s++) heap[s * 64 + lane] = 0;
+        for (int s = 0; s < kSlots; s++) heap[s * 64 + lane] = 0;
         int slot = 0;
         for (int k = 0; k < HOP_BUCKET && slot < hs; k++) {
             if (k == lane) continue;
@@ -535,7 +609,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     auto insert_marked = [&](uint64_t pass, bool wrap) {
         bool have = pass != 0;
         uint64_t key = next_key(pass, wrap);
-        if (hs == kHeapMax) {
+        if (!BIG && hs == kHeapMax) {
             while (__any(have)) {
                 const bool have_next = pass != 0;
                 const uint64_t key_next = next_key(pass, wrap);
@@ -638,9 +712,9 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     }
 
     // 2. breadth-first walk: keep the nodes within a group's bound of that
-    //    group's box; 64 lanes test 64 children at once.  The frontier uses
-    //    the heap's LDS levels, so levels 2-3 of the heap are parked in
-    //    registers meanwhile.
+    //    group's box; 64 lanes test 64 children at once.  In the default
+    //    kernels the frontier uses the heap's LDS levels, so levels 2-3 of
+    //    the heap are parked in registers meanwhile.
     NodeBox bb;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
@@ -653,9 +727,11 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         }
     }
     // park heap levels 2..3 (slots 5..hs-1) in registers
-    uint64_t park[kHeapMax - 5];
+    uint64_t park[BIG ? 1 : kHeapMax - 5];
+    if constexpr (!BIG) {
 #pragma unroll
-    for (int s = 5; s < kHeapMax; s++) park[s - 5] = s < hs ? heap[s * 64 + lane] : 0;
+        for (int s = 5; s < kHeapMax; s++) park[s - 5] = s < hs ? heap[s * 64 + lane] : 0;
+    }
     __syncthreads();
     int fcnt = 1, hf = a.lv.top;
     uint32_t *fc = front_a, *fn = front_b;
@@ -687,7 +763,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
             }
             const uint64_t m = __ballot(need);
             const int pos = ncnt + (int)__popcll(m & lt_mask);
-            if (need && pos < kFrontLevel) fn[pos] = child;
+            if (need && pos < kFL) fn[pos] = child;
             ncnt += (int)__popcll(m);
             n_nodes += 64;
         }
@@ -750,10 +826,12 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     }
     __syncthreads();
     // unpark the heap
+    if constexpr (!BIG) {
 #pragma unroll
-    for (int s = 5; s < kHeapMax; s++)
-        if (s < hs) heap[s * 64 + lane] = park[s - 5];
-    for (int s = hs; s < kHeapSlots; s++) heap[s * 64 + lane] = 0;
+        for (int s = 5; s < kHeapMax; s++)
+            if (s < hs) heap[s * 64 + lane] = park[s - 5];
+        for (int s = hs; s < kSlots; s++) heap[s * 64 + lane] = 0;
+    }
     __syncthreads();
     // 3. stream the listed leaves, 4 leaves (64 particles) per batch,
     //    loading batch b+1 while batch b is tested.  When every relevant
@@ -938,6 +1016,60 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     }
     if (!active || miss) return;
 
+    const int32_t jq = me.j;
+    if constexpr (BIG) {
+        // in-place heapsort in LDS: the keys ascending in slots [0, hs)
+        for (int e = hs - 1; e >= 1; e--) {
+            const uint64_t top = heap[lane], last = heap[e * 64 + lane];
+            heap[e * 64 + lane] = top;
+            lds_sift_size(heap, lane, e, 0, last);
+        }
+        auto d2_at = [&](int t) -> uint64_t { return heap[t * 64 + lane] >> a.shift; };
+        const uint64_t R = d2_at(hs - 1);
+        if (R == 0) atomicOr(a.dflags, DERR_DEGENERATE);
+        if ((double)R >= a.maxd2) atomicOr(a.dflags, DERR_KEYWIDTH);
+        const double Rd = (double)(R == 0 ? 1 : R);
+        double delta;
+        if (!a.fp32) {
+            const double wsum = pairwise_spline<128, double>(a.n_dens, Rd, d2_at, m4_shape);
+            const double h2 = Rd * 0.25;
+            const double hh = __builtin_sqrt(h2);
+            const double h3 = h2 * hh;
+            delta = (wsum * norm) / h3;
+        } else {
+            const float Rf = (float)Rd;
+            const float wsum = pairwise_spline<128, float>(a.n_dens, Rf, d2_at, m4_shape_f32);
+            const float h2 = Rf * 0.25f;
+            const float hh = __builtin_sqrtf(h2);
+            const float h3 = h2 * hh;
+            delta = (double)((wsum * norm32) / h3);
+        }
+        a.dens[jq] = delta;
+        auto col = [&](int t) -> int32_t {
+            if (t == 0) return jq;
+            const uint32_t tkv = (uint32_t)(heap[(t - 1) * 64 + lane] & a.tk_mask);
+            // an unfilled slot (flagged above) must not index the table
+            if (tkv >= (uint64_t)a.n) return -1;
+            return IDS ? a.tk2j[tkv] : (int32_t)tkv;
+        };
+        if (a.nbr16s) {
+            int4 *dst = reinterpret_cast<int4 *>(a.nbr16s + (b0 + lane) * 16);
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                dst[q] = make_int4(col(4 * q), col(4 * q + 1), col(4 * q + 2), col(4 * q + 3));
+            a.dens_s[b0 + lane] = delta;
+        }
+        if (a.nbr) {
+            int32_t *row = a.nbr + (int64_t)jq * a.k_store;
+            if (a.vec_store) {
+                for (int t = 0; t < a.k_store; t += 4)
+                    *reinterpret_cast<int4 *>(row + t) = make_int4(col(t), col(t + 1), col(t + 2), col(t + 3));
+            } else {
+                for (int t = 0; t < a.k_store; t++) row[t] = col(t);
+            }
+        }
+        return;
+    } else {
     // sort the heap ascending in registers (bitonic network over 64 slots)
     uint64_t v[64];
 #pragma unroll
@@ -969,32 +1101,10 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     if (R == 0) atomicOr(a.dflags, DERR_DEGENERATE);
     if ((double)R >= a.maxd2) atomicOr(a.dflags, DERR_KEYWIDTH);
     const double Rd = (double)(R == 0 ? 1 : R);
+    auto d2_at = [&](int t) -> uint64_t { return v[t] >> a.shift; };
     double delta;
     if (!a.fp32) {
-        double part[7];
-#pragma unroll
-        for (int t = 0; t < 64; t++) {
-            double w;
-            if (t == 0) {
-                w = m4_shape(0.0);
-            } else if (t < a.n_dens) {
-                const uint64_t d2 = v[t - 1] >> a.shift;
-                w = m4_shape((double)(4 * d2) / Rd);
-            } else {
-                w = 0.0;
-            }
-            // pairwise (binary-counter) accumulation: T(a,b) = T(a,m) + T(m,b)
-            double s = w;
-            int lvl = 0;
-#pragma unroll
-            for (int b = 0; b < 6; b++) {
-                if (((t >> b) & 1) == 0) break;
-                s = part[b] + s;
-                lvl = b + 1;
-            }
-            part[lvl] = s;
-        }
-        const double wsum = part[6];
+        const double wsum = pairwise_spline<64, double>(a.n_dens, Rd, d2_at, m4_shape);
         const double h2 = Rd * 0.25;
         const double hh = __builtin_sqrt(h2);
         const double h3 = h2 * hh;
@@ -1003,42 +1113,20 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         // same operation sequence in FP32; 4 d^2 and r_max^2 are rounded to
         // FP32 on conversion, everything after runs in FP32
         const float Rf = (float)Rd;
-        float part[7];
-#pragma unroll
-        for (int t = 0; t < 64; t++) {
-            float w;
-            if (t == 0) {
-                w = m4_shape_f32(0.0f);
-            } else if (t < a.n_dens) {
-                const uint64_t d2 = v[t - 1] >> a.shift;
-                w = m4_shape_f32((float)(4 * d2) / Rf);
-            } else {
-                w = 0.0f;
-            }
-            float s = w;
-            int lvl = 0;
-#pragma unroll
-            for (int b = 0; b < 6; b++) {
-                if (((t >> b) & 1) == 0) break;
-                s = part[b] + s;
-                lvl = b + 1;
-            }
-            part[lvl] = s;
-        }
+        const float wsum = pairwise_spline<64, float>(a.n_dens, Rf, d2_at, m4_shape_f32);
         const float h2 = Rf * 0.25f;
         const float hh = __builtin_sqrtf(h2);
         const float h3 = h2 * hh;
-        delta = (double)((part[6] * norm32) / h3);
+        delta = (double)((wsum * norm32) / h3);
     }
 
-    const int32_t jq = me.j;
     a.dens[jq] = delta;
     auto col = [&](int t) -> int32_t {
         if (t == 0) return jq;
         const uint32_t tkv = (uint32_t)(v[t - 1] & a.tk_mask);
         // an unfilled slot (flagged above) must not index the table
-        if (IDS) return tkv < (uint64_t)a.n ? a.tk2j[tkv] : -1;
-        return (int32_t)tkv;
+        if (tkv >= (uint64_t)a.n) return -1;
+        return IDS ? a.tk2j[tkv] : (int32_t)tkv;
     };
     if (a.nbr16s) {
         int4 *dst = reinterpret_cast<int4 *>(a.nbr16s + (b0 + lane) * 16);
@@ -1063,15 +1151,17 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
                 if (t < a.k_store) row[t] = col(t);
         }
     }
+    }
 }
 
 // One box: one wave per bucket of 64 sorted particles.  Consecutive blocks
 // land on different XCDs, so each XCD gets a contiguous run of buckets
 // (neighbouring buckets share candidate leaves in that XCD's L2).
-template <bool PERIODIC, bool IDS>
+template <bool PERIODIC, bool IDS, bool BIG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_density(KnnArgs a)
 {
-    __shared__ uint64_t heap[kHeapSlots * 64];
+    __shared__ uint64_t heap[heap_slots<BIG>() * 64];
+    __shared__ uint32_t front[BIG ? 2 * kFrontLevelBig : 1];
     __shared__ SortedRec stage[64];
     __shared__ double stage_pp[64];
     __shared__ uint32_t leaves[kLeafList];
@@ -1079,24 +1169,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     const int64_t bucket = (bid & 7) * a.xcd_chunk + (bid >> 3);
     if (bucket >= a.n_buckets) return;
     const int64_t b0 = bucket * HOP_BUCKET;
-    knn_bucket<PERIODIC, IDS>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n, a.norm,
-                              a.norm32, heap, stage, stage_pp, leaves, ~0ull, bucket);
+    knn_bucket<PERIODIC, IDS, BIG>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n, a.norm,
+                                   a.norm32, heap, front, stage, stage_pp, leaves, ~0ull, bucket);
 }
 
 // Fallback of a bounded search: the listed buckets again, without a radius,
 // for the lanes recorded in miss[bucket] only.
-template <bool PERIODIC, bool IDS>
+template <bool PERIODIC, bool IDS, bool BIG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_redo(
     KnnArgs a, const uint32_t *__restrict__ list, const unsigned long long *__restrict__ miss)
 {
-    __shared__ uint64_t heap[kHeapSlots * 64];
+    __shared__ uint64_t heap[heap_slots<BIG>() * 64];
+    __shared__ uint32_t front[BIG ? 2 * kFrontLevelBig : 1];
     __shared__ SortedRec stage[64];
     __shared__ double stage_pp[64];
     __shared__ uint32_t leaves[kLeafList];
     const int64_t bucket = list[blockIdx.x];
     const int64_t b0 = bucket * HOP_BUCKET;
-    knn_bucket<PERIODIC, IDS>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n, a.norm,
-                              a.norm32, heap, stage, stage_pp, leaves, miss[bucket], bucket);
+    knn_bucket<PERIODIC, IDS, BIG>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n, a.norm,
+                                   a.norm32, heap, front, stage, stage_pp, leaves, miss[bucket],
+                                   bucket);
 }
 
 // buckets with a recorded miss -> list; count the missed lanes
@@ -1116,11 +1208,12 @@ __global__ void k_miss_list(int64_t n_buckets, const unsigned long long *__restr
 // (largest first by default) and cut into one contiguous chunk per XCD;
 // a wave takes items from its XCD's chunk and, when that runs dry, from the
 // next chunks in turn, and exits when all are dry.
-template <bool PERIODIC>
+template <bool PERIODIC, bool BIG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_batch(KnnArgs a,
                                                                                              BatchArgs b)
 {
-    __shared__ uint64_t heap[kHeapSlots * 64];
+    __shared__ uint64_t heap[heap_slots<BIG>() * 64];
+    __shared__ uint32_t front[BIG ? 2 * kFrontLevelBig : 1];
     __shared__ SortedRec stage[64];
     __shared__ double stage_pp[64];
     __shared__ uint32_t leaves[kLeafList];
@@ -1150,8 +1243,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         const int64_t plo = b.sub_off[sv], phi = b.sub_off[sv + 1];
         const int64_t b0 = plo + (item - b.item_off[lo]) * HOP_BUCKET;
         __syncthreads();
-        knn_bucket<PERIODIC, false>(a, b0, (int)min((int64_t)HOP_BUCKET, phi - b0), plo, phi,
-                                    b.norm[sv], b.norm32[sv], heap, stage, stage_pp, leaves, ~0ull, 0);
+        knn_bucket<PERIODIC, false, BIG>(a, b0, (int)min((int64_t)HOP_BUCKET, phi - b0), plo, phi,
+                                         b.norm[sv], b.norm32[sv], heap, front, stage, stage_pp,
+                                         leaves, ~0ull, 0);
         if (lane == 0) atomicAdd(&b.done[sv], 1u);
     }
 }
@@ -1384,12 +1478,21 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     HOPTRY(start_counters(ctx, a, s));
     const int64_t grid = a.xcd_chunk * 8;
     if (grid >= ((int64_t)1 << 31)) return hop_fail(ctx, HOP_ERR_ARG, "too many particles");
-    if (periodic) {
-        if (id) k_knn_density<true, true><<<(int)grid, 64, 0, s>>>(a);
-        else k_knn_density<true, false><<<(int)grid, 64, 0, s>>>(a);
+    const bool big = p->n_dens > kHeapMax + 1;
+    if (big) {
+        if (periodic) {
+            if (id) k_knn_density<true, true, true><<<(int)grid, 64, 0, s>>>(a);
+            else k_knn_density<true, false, true><<<(int)grid, 64, 0, s>>>(a);
+        } else {
+            if (id) k_knn_density<false, true, true><<<(int)grid, 64, 0, s>>>(a);
+            else k_knn_density<false, false, true><<<(int)grid, 64, 0, s>>>(a);
+        }
+    } else if (periodic) {
+        if (id) k_knn_density<true, true, false><<<(int)grid, 64, 0, s>>>(a);
+        else k_knn_density<true, false, false><<<(int)grid, 64, 0, s>>>(a);
     } else {
-        if (id) k_knn_density<false, true><<<(int)grid, 64, 0, s>>>(a);
-        else k_knn_density<false, false><<<(int)grid, 64, 0, s>>>(a);
+        if (id) k_knn_density<false, true, false><<<(int)grid, 64, 0, s>>>(a);
+        else k_knn_density<false, false, false><<<(int)grid, 64, 0, s>>>(a);
     }
     HOPCHK(ctx, hipGetLastError());
     int64_t misses = 0, redo = 0;
@@ -1407,12 +1510,20 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
         if (redo > 0) {
             KnnArgs r = a;
             r.cell_r = nullptr;
-            if (periodic) {
-                if (id) k_knn_redo<true, true><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
-                else k_knn_redo<true, false><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
+            if (big) {
+                if (periodic) {
+                    if (id) k_knn_redo<true, true, true><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
+                    else k_knn_redo<true, false, true><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
+                } else {
+                    if (id) k_knn_redo<false, true, true><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
+                    else k_knn_redo<false, false, true><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
+                }
+            } else if (periodic) {
+                if (id) k_knn_redo<true, true, false><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
+                else k_knn_redo<true, false, false><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
             } else {
-                if (id) k_knn_redo<false, true><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
-                else k_knn_redo<false, false><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
+                if (id) k_knn_redo<false, true, false><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
+                else k_knn_redo<false, false, false><<<(int)redo, 64, 0, s>>>(r, list, a.miss);
             }
             HOPCHK(ctx, hipGetLastError());
         }
@@ -1514,10 +1625,20 @@ int hop_density_batch_impl(hop_ctx *ctx, int32_t n_sub, const int64_t *off, cons
     b.n_items = item_off[n_sub];
     b.n_sub = n_sub;
     b.xcd_queues = ctx->tuning.xcd_queues ? 1 : 0;
-    int waves = ctx->tuning.persistent_waves > 0 ? ctx->tuning.persistent_waves : 4 * ctx->n_cu;
+    // one wave per SIMD fits the default kernel's LDS; the n_dens > 64
+    // kernel's larger heap leaves room for two waves per compute unit
+    const bool big = p->n_dens > kHeapMax + 1;
+    int waves = ctx->tuning.persistent_waves > 0 ? ctx->tuning.persistent_waves
+                                                 : (big ? 2 : 4) * ctx->n_cu;
     if (waves < 8) waves = 8;
-    if (periodic) k_knn_batch<true><<<waves, 64, 0, s>>>(a, b);
-    else k_knn_batch<false><<<waves, 64, 0, s>>>(a, b);
+    if (big) {
+        if (periodic) k_knn_batch<true, true><<<waves, 64, 0, s>>>(a, b);
+        else k_knn_batch<false, true><<<waves, 64, 0, s>>>(a, b);
+    } else if (periodic) {
+        k_knn_batch<true, false><<<waves, 64, 0, s>>>(a, b);
+    } else {
+        k_knn_batch<false, false><<<waves, 64, 0, s>>>(a, b);
+    }
     HOPCHK(ctx, hipGetLastError());
     if (ctx->profiling) HOPCHK(ctx, hipEventRecord(ev.e[2], s));
 

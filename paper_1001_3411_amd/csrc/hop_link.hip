@@ -169,13 +169,19 @@ __global__ void k_jump(int64_t n, int32_t *__restrict__ root, uint8_t *__restric
     if (fin) done[i] = 1;
 }
 
-__global__ void k_chain_flags(int64_t n, const int32_t *__restrict__ root,
-                              const double *__restrict__ dens, const int32_t *__restrict__ tk,
-                              double delta_outer, uint32_t *__restrict__ flag)
+// Chain roots, flagged by tie key.  After the jumps every root must be a
+// self-linked particle; links that close a cycle (which uphill links never
+// do) leave roots that are not, and raise DERR_CYCLE.
+__global__ void k_chain_flags(int64_t n, const int32_t *__restrict__ hop,
+                              const int32_t *__restrict__ root, const double *__restrict__ dens,
+                              const int32_t *__restrict__ tk, double delta_outer,
+                              uint32_t *__restrict__ flag, uint32_t *__restrict__ dflags)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint32_t f = (root[i] == (int32_t)i && dens[i] >= delta_outer) ? 1u : 0u;
+    const int32_t r = root[i];
+    if (hop[r] != r) atomicOr(dflags, DERR_CYCLE);
+    uint32_t f = (r == (int32_t)i && hop[i] == (int32_t)i && dens[i] >= delta_outer) ? 1u : 0u;
     flag[tk ? tk[i] : i] = f;
 }
 
@@ -236,34 +242,37 @@ int hop_link_sorted_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr16s, const d
     return HOP_OK;
 }
 
-int hop_groups_impl(hop_ctx *ctx, int64_t n, const int32_t *hop, const double *density,
-                    const int32_t *tk, const hop_params *p, int32_t *root, int32_t *chain_of,
-                    int32_t *n_chains, hipStream_t s)
+int hop_jump_impl(hop_ctx *ctx, int64_t n, int32_t *root, hipStream_t s)
 {
-    uint32_t *dflags = (uint32_t *)ctx->flags.ptr;
-    uint32_t *changed = dflags + 1;
-    uint32_t *total = dflags + 2;
-    k_root_init<<<hop_grid(n, 256), 256, 0, s>>>(n, hop, root, dflags);
-    HOPCHK(ctx, hipGetLastError());
+    uint32_t *changed = (uint32_t *)ctx->flags.ptr + 1;
     HOPTRY(hop_reserve(ctx, ctx->jump_done, (size_t)n));
     uint8_t *done = (uint8_t *)ctx->jump_done.ptr;
     HOPCHK(ctx, hipMemsetAsync(done, 0, (size_t)n, s));
-    int rounds = 0;
-    for (;;) {
+    for (int rounds = 0;; rounds++) {
         HOPCHK(ctx, hipMemsetAsync(changed, 0, 4, s));
         k_jump<<<hop_grid(n, 256), 256, 0, s>>>(n, root, done, changed);
         HOPCHK(ctx, hipGetLastError());
         HOPCHK(ctx, hipMemcpyAsync(ctx->hflags, changed, 4, hipMemcpyDeviceToHost, s));
         HOPCHK(ctx, hipStreamSynchronize(s));
-        if (((uint32_t *)ctx->hflags)[0] == 0u) break;
-        if (++rounds > 40) {
-            // 4 jumps per round: 40 rounds resolve any chain shorter than 2^80
-            return hop_fail(ctx, HOP_ERR_ARG, "links do not reach a self-linked particle");
-        }
+        if (((uint32_t *)ctx->hflags)[0] == 0u) return HOP_OK;
+        // 4 jumps per round: 40 rounds resolve any chain shorter than 2^80
+        if (rounds >= 40) return hop_fail(ctx, HOP_ERR_ARG, "links do not reach a self-linked particle");
     }
+}
+
+int hop_groups_impl(hop_ctx *ctx, int64_t n, const int32_t *hop, const double *density,
+                    const int32_t *tk, const hop_params *p, int32_t *root, int32_t *chain_of,
+                    int32_t *n_chains, hipStream_t s)
+{
+    uint32_t *dflags = (uint32_t *)ctx->flags.ptr;
+    uint32_t *total = dflags + 2;
+    k_root_init<<<hop_grid(n, 256), 256, 0, s>>>(n, hop, root, dflags);
+    HOPCHK(ctx, hipGetLastError());
+    HOPTRY(hop_jump_impl(ctx, n, root, s));
     HOPTRY(hop_reserve(ctx, ctx->work_a, (size_t)n * 4));
     uint32_t *flag = (uint32_t *)ctx->work_a.ptr;
-    k_chain_flags<<<hop_grid(n, 256), 256, 0, s>>>(n, root, density, tk, p->delta_outer, flag);
+    k_chain_flags<<<hop_grid(n, 256), 256, 0, s>>>(n, hop, root, density, tk, p->delta_outer, flag,
+                                                   dflags);
     HOPCHK(ctx, hipGetLastError());
     HOPTRY(hop_scan_u32(ctx, flag, n, total, s));
     k_chain_of<<<hop_grid(n, 256), 256, 0, s>>>(n, root, density, tk, p->delta_outer, flag,

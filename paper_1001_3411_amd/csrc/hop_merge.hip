@@ -86,7 +86,7 @@ __global__ void k_saddle_insert(int64_t n, const int32_t *__restrict__ nbr, int 
         const double sv = (di + dens[j]) * 0.5;
         const unsigned long long sb = (unsigned long long)__double_as_longlong(sv);
         const uint64_t key = ((uint64_t)(uint32_t)min(ci, cj) << 32) | (uint32_t)max(ci, cj);
-        uint64_t slot = pair_hash(key) >> (64 - log2cap);
+        uint64_t slot = log2cap > 0 ? pair_hash(key) >> (64 - log2cap) : 0;
         bool done = false;
         for (uint64_t probe = 0; probe <= mask; probe++) {
             uint64_t k = hkeys[slot];
@@ -439,14 +439,16 @@ inline int64_t pow2ceil(int64_t v)
 int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
                    const int32_t *root, const int32_t *chain_of, int32_t n_chains,
                    const int32_t *tk, const uint8_t *padded, const hop_params *p, int32_t *group,
-                   int32_t *n_groups, hop_group_info *groups, const int32_t *chain_base,
-                   int32_t n_sub, int32_t *group_first, hipStream_t s)
+                   int32_t *n_groups, hop_group_info *groups, const MergeExtra &x, hipStream_t s)
 {
+    const int32_t *chain_base = x.chain_base;
+    const int32_t n_sub = x.n_sub;
+    int32_t *group_first = x.group_first;
     uint32_t *dflags = (uint32_t *)ctx->flags.ptr;
     uint32_t *dcnt = dflags + 4;  // [0] edges, [1] msf edges, [2] halos
     const int32_t C = n_chains;
     const int pr = (p->flags & HOP_PADDED_RULES) ? 1 : 0;
-    const int32_t *tk2j = tk ? (const int32_t *)ctx->tk2j.ptr : nullptr;
+    const int32_t *tk2j = (tk && !x.tk_is_index) ? (const int32_t *)ctx->tk2j.ptr : nullptr;
     if (C <= 0) {
         k_fill_i32<<<hop_grid(n, 256), 256, 0, s>>>(group, n, -1);
         HOPCHK(ctx, hipGetLastError());
@@ -482,7 +484,9 @@ int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *de
 
     // --- boundary table -----------------------------------------------------
     const int64_t pairs_max = (int64_t)(p->n_merge - 1) * n;
-    int64_t cap = pow2ceil(std::max<int64_t>(4096, std::min<int64_t>(16 * (int64_t)C, 2 * pairs_max + 1)));
+    int64_t cap = ctx->tuning.hash_slots > 0
+                      ? pow2ceil(ctx->tuning.hash_slots)
+                      : pow2ceil(std::max<int64_t>(4096, std::min<int64_t>(16 * (int64_t)C, 2 * pairs_max + 1)));
     const int64_t cap_max = pow2ceil(2 * pairs_max + 1);
     int64_t E = 0;
     for (;;) {
@@ -555,6 +559,7 @@ int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *de
     if (E > 0)
         k_union_saddle<<<hop_grid(E, 256), 256, 0, s>>>(E, elo, ehi, es, cpeak, p->delta_peak,
                                                         p->delta_saddle, hp);
+    if (x.n_pre > 0) k_union_msf<<<hop_grid(x.n_pre, 256), 256, 0, s>>>(x.n_pre, x.pre_lo, x.pre_hi, hp);
     k_compress<<<hop_grid(C, 256), 256, 0, s>>>(C, hp);
     HOPCHK(ctx, hipMemsetAsync(rooted, 0, (size_t)C * 4, s));
     k_rooted<<<hop_grid(C, 256), 256, 0, s>>>(C, hp, cpeak, p->delta_peak, rooted);

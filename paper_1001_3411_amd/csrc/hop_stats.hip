@@ -82,15 +82,23 @@ k_stats_sum(int64_t n, const uint32_t *__restrict__ pos, const float *__restrict
 }
 
 // per halo: mean offset, centre, bulk velocity
-__global__ void k_stats_halo(int32_t n_groups, const uint32_t *__restrict__ pos,
+// A group whose peak lies outside [0, n) (a table that does not belong to
+// these particles) gets no centre and sets DERR_INDEX; nothing is read at
+// the bad index.
+__global__ void k_stats_halo(int64_t n, int32_t n_groups, const uint32_t *__restrict__ pos,
                              const hop_group_info *__restrict__ groups, int periodic, int64_t G,
                              const unsigned long long *__restrict__ osum, const double *__restrict__ vsum,
-                             double *__restrict__ mean, double *__restrict__ com, double *__restrict__ vbulk)
+                             double *__restrict__ mean, double *__restrict__ com, double *__restrict__ vbulk,
+                             uint32_t *__restrict__ dflags)
 {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_groups) return;
     const double c = (double)groups[g].count;
     const int64_t p = groups[g].peak;
+    if (p < 0 || p >= n) {
+        atomicOr(dflags, DERR_INDEX);
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         const double m = (double)(int64_t)osum[3 * g + k] / c;
@@ -170,11 +178,12 @@ extern "C" int hop_halo_stats(hop_ctx *ctx, int64_t n, const uint32_t *pos, cons
     k_stats_sum<<<grid, kStatsBlock, 0, s>>>(n, pos, vel, group, n_groups, groups, periodic, G, osum,
                                                  vel ? vsum : nullptr, (uint32_t *)ctx->flags.ptr);
     HOPCHK(ctx, hipGetLastError());
-    k_stats_halo<<<hop_grid(n_groups, 256), 256, 0, s>>>(n_groups, pos, groups, periodic, G, osum, vsum,
-                                                         mean, com, vel ? vbulk : nullptr);
+    k_stats_halo<<<hop_grid(n_groups, 256), 256, 0, s>>>(n, n_groups, pos, groups, periodic, G, osum,
+                                                         vsum, mean, com, vel ? vbulk : nullptr,
+                                                         (uint32_t *)ctx->flags.ptr);
     HOPCHK(ctx, hipGetLastError());
     k_stats_radius<<<grid, kStatsBlock, 0, s>>>(n, pos, group, n_groups, groups, periodic, G, mean,
                                                     (unsigned long long *)rmax);
     HOPCHK(ctx, hipGetLastError());
-    return HOP_OK;
+    return hop_check_device(ctx, s, "hop_halo_stats");
 }

@@ -45,7 +45,8 @@ def test_null_context_is_rejected_without_device():
                                 None) == -1
     assert lib.hop_halo_stats(None, 100, None, None, None, 1, None, ctypes.byref(p), None, None,
                               None, None) == -1
-    assert lib.hop_stitch(None, 1, None, None, None, None, None, 64, 100, None, None, None) == -1
+    assert lib.hop_stitch(None, 1, None, None, None, None, None, None, ctypes.byref(p), 0, 100,
+                          None, None, None, None, None, None, None, None, None) == -1
     assert lib.hop_last_error(None) == b"no context"
 
 

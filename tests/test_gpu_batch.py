@@ -104,3 +104,23 @@ def test_batch_64_subvolumes_full(ctx, orc):
     print(f"[batch] 64 subvolumes, {sum(p.n for p in subs)} particles", flush=True)
     g = run_batch(ctx, subs)
     check_against_oracle(orc, subs, g, "config4")
+
+
+def test_batch_many_small_subvolumes_every_setting_matches_oracle(ctx, orc):
+    """Regression for wrong lists seen once in the persistent kernel: many
+    small subvolumes make each wave run buckets of different subvolumes one
+    after another (state left from the previous bucket would show), under
+    launch settings that change which wave runs which bucket.  Every setting
+    is checked against the oracle, subvolume by subvolume."""
+    subs = [synth.padded_subvolume(n, 4400 + i)
+            for i, n in enumerate((13233, 64, 65, 127, 700, 2049, 5000, 9001, 13233, 301))]
+    settings = (dict(), dict(persistent_waves=8), dict(persistent_waves=37, front_cap=4),
+                dict(persistent_waves=1024, xcd_queues=0), dict(largest_first=0, front_cap=64),
+                dict(persistent_waves=64, xcd_queues=0, largest_first=0))
+    for t in settings:
+        ctx.set_tuning(**t)
+        try:
+            g = run_batch(ctx, subs)
+        finally:
+            ctx.set_tuning(front_cap=1024, persistent_waves=0, xcd_queues=1, largest_first=1)
+        check_against_oracle(orc, subs, g, f"setting {t}")

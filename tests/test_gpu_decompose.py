@@ -1,11 +1,13 @@
-"""The decomposition front end end to end: a periodic box cut into 8
+"""The decomposition front end and the stitching end to end, against the
+oracle's whole-box run of the 2,097,152-particle box.  Cut into 8
 load-balanced, directionally padded subvolumes and run through the batched
-call must give every core particle whose whole-box neighbour sphere lies
-inside its padded subvolume exactly the whole-box density (same neighbours
-at the same exact distances, same global mean density, same operation
-sequence).  Particles nearer the padded box's edge than their 64th
-neighbour are only counted: how many there are is what the safety factor
-s of Eq. (1) controls.
+call, every core particle whose whole-box neighbour sphere lies inside its
+padded subvolume gets exactly the whole-box density (same neighbours at the
+same exact distances, same global mean density, same operation sequence);
+particles nearer the padded box's edge than their 64th neighbour are only
+counted: how many there are is what the safety factor s of Eq. (1)
+controls.  Stitched (chains rebuilt through padded particles, one boundary
+table, one merge), every whole-box output is reproduced.
 """
 import numpy as np
 import pytest
@@ -13,6 +15,12 @@ import pytest
 import synth
 
 pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def box2(orc):
+    p = synth.config(2)
+    return p, orc.run(p.pos, mean_density=p.mean_density)
 
 
 @pytest.fixture(scope="module")
@@ -26,15 +34,13 @@ def ctx():
     c.close()
 
 
-def test_padded_subvolumes_reproduce_box_densities(ctx):
+def test_padded_subvolumes_reproduce_box_densities(ctx, box2):
     from paper_1001_3411_amd import HopParams
     from paper_1001_3411_amd.decompose import decompose
     G = 1 << 21
-    p = synth.config(2)
-    full = HopParams(mean_density=p.mean_density)
-    dens_full, nbr_full = ctx.density(p.pos, full)
-    dens_full = dens_full.cpu().numpy()
-    far = nbr_full[:, -1].cpu().numpy()
+    p, r = box2
+    dens_full = r.density
+    far = r.nbr[:, -1]
     d = decompose(p.pos, 8, seed=3)
     sub = HopParams(periodic=False, padded_rules=True, mean_density=p.mean_density)
     out = ctx.run_batch(d.pos, d.offsets, sub, padded=d.padded,
@@ -62,21 +68,16 @@ def test_padded_subvolumes_reproduce_box_densities(ctx):
     assert checked > 0.9 * p.n
 
 
-def test_stitched_pipeline_equals_whole_box(ctx):
-    """Decompose, run the subvolumes in one batched call, stitch their core
-    rows into box arrays (hop_stitch), and run links, chains and the merge
-    on the box: every output equals the whole-box run."""
+def _stitched(ctx, p, premerge):
     import time
 
     import torch
 
     from paper_1001_3411_amd import HopParams
     from paper_1001_3411_amd.decompose import decompose
-    p = synth.config(2)
-    full = HopParams(mean_density=p.mean_density)
-    ref = ctx.run(p.pos, full)
-    d = decompose(p.pos, 8, seed=3)
+    d = decompose(p.pos, 8, seed=3, safety=1.5)
     sub = HopParams(periodic=False, padded_rules=True, mean_density=p.mean_density)
+    box = HopParams(periodic=False, padded_rules=True, mean_density=p.mean_density)
     pos_b = torch.from_numpy(d.pos.view(np.int32)).cuda()
     pad_b = torch.from_numpy(d.padded).cuda()
     idx_b = torch.from_numpy(d.index).cuda()
@@ -84,17 +85,40 @@ def test_stitched_pipeline_equals_whole_box(ctx):
     for rep in range(2):   # the second pass is timed
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = ctx.run_batch(pos_b, d.offsets, sub, padded=pad_b, mean_density=md)
-        dens, nbr = ctx.stitch(d.offsets, idx_b, pad_b, out["density"], out["nbr"], p.n)
-        hop = ctx.link(nbr, dens, full)
-        root, chain_of, nc = ctx.groups(hop, dens, full)
-        m = ctx.merge(nbr, dens, root, chain_of, nc, full)
+        b = ctx.run_batch(pos_b, d.offsets, sub, padded=pad_b, mean_density=md)
+        out = ctx.stitch(d.offsets, idx_b, pad_b, b, p.n, box, premerge=premerge)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-    print(f"[stitch] {p.n} particles, 8 subvolumes ({d.pos.shape[0]} rows with padding): "
-          f"{dt * 1e3:.1f} ms; {m['n_groups']} groups", flush=True)
-    for k, a in (("density", dens), ("nbr", nbr), ("hop", hop), ("root", root),
-                 ("chain_of", chain_of), ("group", m["group"]), ("g_count", m["g_count"]),
-                 ("g_peak", m["g_peak"])):
-        assert torch.equal(a, ref[k]), k
-    assert nc == ref["n_chains"] and m["n_groups"] == ref["n_groups"]
+    print(f"[stitch] premerge={premerge}: {p.n} particles, 8 subvolumes "
+          f"({d.pos.shape[0]} rows with padding): {dt * 1e3:.1f} ms; {out['n_chains']} chains, "
+          f"{out['n_groups']} groups, {ctx.stats()['premerged']} premerged pairs", flush=True)
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
+
+
+def test_stitched_chains_equal_whole_box(ctx, box2):
+    """Decompose (s = 1.5), run the subvolumes in one batched call, then
+    rebuild the chains through the padded particles they end on, give
+    padded particles their owners' chains, build one boundary table from
+    every subvolume's rows and merge (hop_stitch, no premerge): every output
+    equals the oracle's whole-box run."""
+    p, r = box2
+    g = _stitched(ctx, p, premerge=False)
+    for k in ("density", "hop", "root", "chain_of", "group", "g_count", "g_peak", "g_peak_dens"):
+        assert np.array_equal(g[k], getattr(r, k)), k
+    assert g["n_chains"] == r.n_chains and g["n_groups"] == r.n_groups
+
+
+def test_stitched_with_premerge(ctx, box2):
+    """The premerge joins proto-halos inside each subvolume before the
+    chains are reconnected; a join the whole box would not make can only
+    come from a padded particle's density, so the labels should barely
+    change: the fraction of particles whose group changes is reported."""
+    from paper_1001_3411_amd.report import group_change_fraction
+    p, r = box2
+    g = _stitched(ctx, p, premerge=True)
+    for k in ("density", "hop", "root", "chain_of"):
+        assert np.array_equal(g[k], getattr(r, k)), k
+    chg = group_change_fraction(r.group, g["group"])
+    print(f"[stitch] premerge group change fraction {chg:.3e} "
+          f"({g['n_groups']} vs {r.n_groups} groups)", flush=True)
+    assert chg < 1e-3
