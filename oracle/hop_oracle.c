@@ -785,6 +785,175 @@ int orc_labels(int64_t n, const int32_t *chain_of, int64_t n_chains, const int32
 }
 
 /* ------------------------------------------------------------------------ */
+/* 8. subhalos (ADAPTAHOP-style extension, section 6)                        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The paper sketches subhalo finding as an extension: chains are found as in
+ * HOP; only "symmetric" boundaries between chains are kept (both chains
+ * link to the other); boundaries below a level delta_s are destroyed; the
+ * remaining structure at each level gives the subhalos; structures below
+ * the level of Poisson noise are rejected; several levels give a hierarchy.
+ * It fixes no formulas; the readings taken here:
+ *   - directed boundary A->B: the maximum of 0.5 (delta_i + delta_j) over
+ *     chained i in A and j in B among nbr[i][1 .. n_merge) (the HOP boundary
+ *     pairs, kept by direction);
+ *   - symmetric boundary {A, B}: present when both A->B and B->A are, with
+ *     density min(D(A->B), D(B->A)): the level down to which each chain
+ *     reaches the other;
+ *   - at level delta_s: chains joined by symmetric boundaries >= delta_s form
+ *     structures; a structure's members are its particles with density >=
+ *     delta_s; its peak is its densest member (ties to the smaller (id,
+ *     index));
+ *   - significance: a structure of N members is kept when its peak density
+ *     is >= delta_s (1 + alpha / sqrt(N)) (alpha = 0 keeps every structure
+ *     with a member);
+ *   - numbering per level as the halos (count desc, peak density desc, peak
+ *     (id, index) asc); parent = the previous level's number of the
+ *     structure holding the peak particle (-1 at the first level or when
+ *     that particle is in none).
+ * Levels must ascend.  sub[l * n + i] = number of particle i's structure at
+ * level l or -1; per level l the tables start at t_off[l] (t_off has
+ * n_levels + 1 entries; capacity n_levels * n_chains).
+ */
+typedef struct {
+    int32_t a, b;  /* ordered: from chain a to chain b */
+    double s;
+} dedge_t;
+
+static int dedge_cmp(const void *x, const void *y)
+{
+    const dedge_t *p = (const dedge_t *)x, *q = (const dedge_t *)y;
+    int32_t pl = p->a < p->b ? p->a : p->b, ph = p->a < p->b ? p->b : p->a;
+    int32_t ql = q->a < q->b ? q->a : q->b, qh = q->a < q->b ? q->b : q->a;
+    if (pl != ql) return pl < ql ? -1 : 1;
+    if (ph != qh) return ph < qh ? -1 : 1;
+    if (p->a != q->a) return p->a < q->a ? -1 : 1;
+    return 0;
+}
+
+int orc_subhalos(int64_t n, int k_cols, int n_merge, const int32_t *nbr, const double *dens,
+                 const int32_t *chain_of, int64_t n_chains, const int64_t *id,
+                 const double *levels, int n_levels, double alpha, int32_t *sub,
+                 int64_t *t_off, int64_t *t_count, int32_t *t_peak, double *t_peak_dens,
+                 int32_t *t_parent, int64_t *n_sym)
+{
+    if (n_merge < 1 || n_merge > k_cols || n_levels < 1 || !(alpha >= 0)) return ORC_ERR_ARG;
+    for (int l = 1; l < n_levels; l++)
+        if (!(levels[l] > levels[l - 1])) return ORC_ERR_ARG;
+    const int64_t C = n_chains;
+    /* 1. directed pairs */
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (chain_of[i] < 0) continue;
+        for (int t = 1; t < n_merge; t++) {
+            int64_t j = nbr[i * k_cols + t];
+            if (chain_of[j] >= 0 && chain_of[j] != chain_of[i]) m++;
+        }
+    }
+    dedge_t *d = (dedge_t *)malloc(sizeof(dedge_t) * (size_t)(m > 0 ? m : 1));
+    int32_t *s_lo = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int32_t *s_hi = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    double *s_v = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    int64_t *par = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C > 0 ? C : 1));
+    grp_t *g = (grp_t *)malloc(sizeof(grp_t) * (size_t)(C > 0 ? C : 1));
+    int32_t *num = (int32_t *)malloc(sizeof(int32_t) * (size_t)(C > 0 ? C : 1));
+    if (!d || !s_lo || !s_hi || !s_v || !par || !g || !num) {
+        free(d); free(s_lo); free(s_hi); free(s_v); free(par); free(g); free(num);
+        return ORC_ERR_NOMEM;
+    }
+    int64_t w = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (chain_of[i] < 0) continue;
+        for (int t = 1; t < n_merge; t++) {
+            int64_t j = nbr[i * k_cols + t];
+            if (chain_of[j] < 0 || chain_of[j] == chain_of[i]) continue;
+            d[w].a = chain_of[i];
+            d[w].b = chain_of[j];
+            d[w].s = (dens[i] + dens[j]) * 0.5;
+            w++;
+        }
+    }
+    /* 2. per unordered pair: the maximum of each direction, kept when both exist */
+    qsort(d, (size_t)m, sizeof(dedge_t), dedge_cmp);
+    int64_t E = 0;
+    for (int64_t r = 0; r < m;) {
+        int32_t lo = d[r].a < d[r].b ? d[r].a : d[r].b, hi = d[r].a < d[r].b ? d[r].b : d[r].a;
+        double up = -1.0, down = -1.0; /* lo -> hi, hi -> lo */
+        int64_t q = r;
+        for (; q < m; q++) {
+            int32_t l2 = d[q].a < d[q].b ? d[q].a : d[q].b, h2 = d[q].a < d[q].b ? d[q].b : d[q].a;
+            if (l2 != lo || h2 != hi) break;
+            if (d[q].a == lo) { if (d[q].s > up) up = d[q].s; }
+            else if (d[q].s > down) down = d[q].s;
+        }
+        if (up >= 0.0 && down >= 0.0) {
+            s_lo[E] = lo;
+            s_hi[E] = hi;
+            s_v[E] = up < down ? up : down;
+            E++;
+        }
+        r = q;
+    }
+    *n_sym = E;
+    /* 3. every level */
+    int64_t base = 0;
+    for (int l = 0; l < n_levels; l++) {
+        const double lev = levels[l];
+        for (int64_t c = 0; c < C; c++) par[c] = c;
+        for (int64_t e = 0; e < E; e++) {
+            if (!(s_v[e] >= lev)) continue;
+            int64_t a = uf_find(par, s_lo[e]), b = uf_find(par, s_hi[e]);
+            if (a == b) continue;
+            if (a < b) par[b] = a; else par[a] = b;
+        }
+        for (int64_t c = 0; c < C; c++) {
+            g[c].count = 0;
+            g[c].peak_dens = -1.0;
+            g[c].peak_id = INT64_MAX;
+            g[c].peak_idx = INT64_MAX;
+            g[c].halo = (int32_t)c;
+            num[c] = -1;
+        }
+        for (int64_t i = 0; i < n; i++) {
+            if (chain_of[i] < 0 || !(dens[i] >= lev)) continue;
+            int64_t r = uf_find(par, chain_of[i]);
+            g[r].count++;
+            int64_t iid = id ? id[i] : i;
+            if (denser(dens[i], iid, i, g[r].peak_dens, g[r].peak_id, g[r].peak_idx)) {
+                g[r].peak_dens = dens[i];
+                g[r].peak_id = iid;
+                g[r].peak_idx = i;
+            }
+        }
+        int64_t G = 0;
+        for (int64_t c = 0; c < C; c++) {
+            if (g[c].count < 1) continue;
+            if (!(g[c].peak_dens >= lev * (1.0 + alpha / sqrt((double)g[c].count)))) continue;
+            g[G++] = g[c];
+        }
+        qsort(g, (size_t)G, sizeof(grp_t), grp_cmp);
+        for (int64_t t = 0; t < G; t++) {
+            num[g[t].halo] = (int32_t)t;
+            t_count[base + t] = g[t].count;
+            t_peak[base + t] = (int32_t)g[t].peak_idx;
+            t_peak_dens[base + t] = g[t].peak_dens;
+            t_parent[base + t] = l > 0 ? sub[(int64_t)(l - 1) * n + g[t].peak_idx] : -1;
+        }
+        for (int64_t i = 0; i < n; i++) {
+            int32_t lab = -1;
+            if (chain_of[i] >= 0 && dens[i] >= lev) lab = num[uf_find(par, chain_of[i])];
+            sub[(int64_t)l * n + i] = lab;
+        }
+        t_off[l] = base;
+        base += G;
+    }
+    t_off[n_levels] = base;
+    free(d); free(s_lo); free(s_hi); free(s_v); free(par); free(g); free(num);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* whole pipeline                                                            */
 /* ------------------------------------------------------------------------ */
 

@@ -16,7 +16,7 @@ from . import build as _build
 
 __all__ = [
     "lib", "knn", "density", "norm", "hop", "chains", "saddles", "merge", "labels",
-    "run", "run_lite", "Lite", "stages", "OracleResult", "LiteResult", "num_threads",
+    "run", "run_lite", "Lite", "stages", "subhalos", "Subhalos", "OracleResult", "LiteResult", "num_threads",
     "set_threads", "HopParams",
 ]
 
@@ -53,6 +53,8 @@ def lib():
         L.orc_lite_end.restype = None
         L.orc_stages.argtypes = [i64, vp, vp, i32, i32, i32, f64, f64, f64, i32, vp, vp, vp, vp,
                                  vp, vp, vp, vp, vp, vp]
+        L.orc_subhalos.argtypes = [i64, i32, i32, vp, vp, vp, i64, vp, vp, i32, f64, vp, vp, vp,
+                                   vp, vp, vp, vp]
         L.orc_num_threads.restype = i32
         L.orc_set_threads.argtypes = [i32]
         L.orc_set_threads.restype = None
@@ -352,3 +354,37 @@ class Lite:
             self.close()
         except Exception:
             pass
+
+
+@dataclass
+class Subhalos:
+    sub: np.ndarray        # [n_levels][n] structure number per level or -1
+    t_off: np.ndarray      # [n_levels + 1] table offsets
+    count: np.ndarray
+    peak: np.ndarray
+    peak_dens: np.ndarray
+    parent: np.ndarray
+    n_sym: int             # symmetric chain boundaries
+
+
+def subhalos(nbr, dens, chain_of, n_chains, levels, n_merge=4, alpha=0.0, ids=None) -> Subhalos:
+    """Subhalos at ascending levels (the readings are in the C source)."""
+    nbr = _c(nbr, np.int32)
+    n, kc = nbr.shape
+    lv = np.ascontiguousarray(np.asarray(levels, dtype=np.float64))
+    L = lv.size
+    cap = max(L * int(n_chains), 1)
+    sub = np.empty((L, n), np.int32)
+    t_off = np.zeros(L + 1, np.int64)
+    cnt = np.empty(cap, np.int64)
+    pk = np.empty(cap, np.int32)
+    pd = np.empty(cap, np.float64)
+    par = np.empty(cap, np.int32)
+    ns = np.zeros(1, np.int64)
+    _check(lib().orc_subhalos(n, kc, int(n_merge), _p(nbr), _p(_c(dens, np.float64)),
+                              _p(_c(chain_of, np.int32)), int(n_chains), _p(_c(ids, np.int64)),
+                              _p(lv), L, float(alpha), _p(sub), _p(t_off), _p(cnt), _p(pk), _p(pd),
+                              _p(par), _p(ns)), "subhalos")
+    g = int(t_off[-1])
+    return Subhalos(sub, t_off, cnt[:g].copy(), pk[:g].copy(), pd[:g].copy(), par[:g].copy(),
+                    int(ns[0]))
