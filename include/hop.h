@@ -15,6 +15,8 @@
  *   hop_stitch   whole-box chains and halos from padded subvolumes   (sec. 3.1)
  *   hop_halo_stats  per-halo count, centre, maximum radius, bulk velocity
  *                (sec. 3.1 output step)
+ *   hop_subhalos substructure at density levels from symmetric chain
+ *                boundaries (the paper's subhalo subsection)
  *
  * Conventions shared by every entry point
  * ----------------------------------------
@@ -255,23 +257,30 @@ int hop_merge(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density
  * self-linked row, the chain's peak.  Chains are the peaks at or above
  * delta_outer, numbered by box index.  Every row takes the chain of its
  * owner; boundaries come from every row and its n_merge - 1 listed
- * neighbours (not both padded), with the rows' own densities; merge and
- * labels then follow hop_merge, counting local rows only.  With premerge,
- * each subvolume first joins its own chains (peaks as that subvolume sees
- * them) that reach delta_peak and share a boundary >= delta_saddle; the
- * final merge keeps those joins.  When every local particle's neighbours
- * and their densities are the whole-box ones (enough padding, rows of each
- * subvolume in increasing box index so that ties go the same way), the
- * outputs equal those of the whole-box run.
+ * neighbours (not both padded); merge and labels then follow hop_merge,
+ * counting local rows only.  Row densities: by default every row takes its
+ * owner's density as well as its chain, and the links of local rows are
+ * formed again from their first n_hop list entries with those densities
+ * (equal densities to the smaller box index), so a padded particle whose
+ * own list was cut short by the padding changes nothing; with
+ * HOP_STITCH_TASK_DENSITIES every row keeps the density its subvolume gave
+ * it and local rows keep hop_b's links, as independent tasks would.  With
+ * HOP_STITCH_PREMERGE each subvolume first joins its own chains (peaks as
+ * that subvolume sees them) that reach delta_peak and share a boundary >=
+ * delta_saddle; the final merge keeps those joins.  By default, when every
+ * local particle's list is its whole-box list (enough padding, rows of each
+ * subvolume in increasing box index so that ties go the same way), every
+ * output equals that of the whole-box run.
  *
  * offsets    HOST [n_sub + 1] row ranges of the batch, offsets[0] = 0
  * index      [rows] int64: the box index of each row
  * padded     [rows] uint8 (nonzero = padding row); required
  * density_b, nbr_b [rows][k_store], hop_b   hop_run_batch outputs (local
- *            to each subvolume)
+ *            to each subvolume); hop_b is read only with
+ *            HOP_STITCH_TASK_DENSITIES (else it may be NULL)
  * p          the box's parameters (HOP_PADDED_RULES required; k_store is
  *            nbr_b's row length)
- * premerge   nonzero: the premerge step above
+ * mode       HOP_STITCH_* bits
  * n          box particles; every box index must be the local row of
  *            exactly one subvolume (else HOP_ERR_ARG)
  * density, hop (or NULL), root, chain_of, group   [n] box outputs, box
@@ -281,9 +290,11 @@ int hop_merge(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density
  * Synchronises `stream`; a row index or link outside its subvolume is
  * HOP_ERR_RANGE.
  */
+#define HOP_STITCH_PREMERGE       0x1
+#define HOP_STITCH_TASK_DENSITIES 0x2
 int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, const int64_t *index,
                const uint8_t *padded, const double *density_b, const int32_t *nbr_b,
-               const int32_t *hop_b, const hop_params *p, int32_t premerge, int64_t n,
+               const int32_t *hop_b, const hop_params *p, int32_t mode, int64_t n,
                double *density, int32_t *hop, int32_t *root, int32_t *chain_of, int32_t *group,
                int32_t *n_chains, int32_t *n_groups, hop_group_info *groups, void *stream);
 
@@ -319,6 +330,45 @@ int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, const int64_
 int hop_halo_stats(hop_ctx *ctx, int64_t n, const uint32_t *pos, const float *vel,
                    const int32_t *group, int32_t n_groups, const hop_group_info *groups,
                    const hop_params *p, double *com, double *rmax, double *vbulk, void *stream);
+
+/*
+ * hop_subhalos -- substructure inside the chains (the ADAPTAHOP-style
+ * extension sketched in the paper's subhalo subsection: symmetric
+ * boundaries between chains, boundary links below a level delta_s
+ * destroyed, structures below the Poisson noise rejected, a hierarchy over
+ * several levels).  The paper gives no formulas; the readings:
+ *   - directed boundary A->B: max of 0.5 (delta_i + delta_j) over chained i
+ *     in A and j in B among nbr[i][1 .. n_merge); symmetric boundary {A, B}
+ *     when both directions exist, density min(D(A->B), D(B->A));
+ *   - at level delta_s: chains joined by symmetric boundaries >= delta_s
+ *     form a structure; its members are its particles with density >=
+ *     delta_s; its peak the densest member (ties to the smaller id);
+ *   - kept when peak density >= delta_s (1 + alpha / sqrt(members));
+ *   - numbered per level like the halos (count desc, peak density desc,
+ *     peak id asc); parent = the previous level's number at the peak
+ *     particle (-1 at the first level or when it has none).
+ * The boundary table is not premerged (all links are needed per level).
+ *
+ * nbr, density, chain_of, n_chains, id   as for hop_merge
+ * levels     HOST [n_levels] ascending delta_s values, 1 <= n_levels <= 64
+ * alpha      significance factor (0 keeps every structure with a member)
+ * sub        [n_levels][n] device output: structure number or -1
+ * t_off      HOST [n_levels + 1] output: level l's structures are table
+ *            entries [t_off[l], t_off[l+1])
+ * table      device [n_levels * n_chains] output, or NULL
+ * Synchronises `stream`.
+ */
+typedef struct hop_subhalo_info {
+    int64_t count;        /* members (density >= the level)          */
+    int32_t peak;         /* input index of the densest member        */
+    int32_t parent;       /* number at the previous level, or -1      */
+    double peak_density;
+} hop_subhalo_info;
+
+int hop_subhalos(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
+                 const int32_t *chain_of, int32_t n_chains, const int64_t *id,
+                 const hop_params *p, int32_t n_levels, const double *levels, double alpha,
+                 int32_t *sub, int64_t *t_off, hop_subhalo_info *table, void *stream);
 
 /*
  * hop_run_batch -- the whole path (density, links, chains, merge, labels)
@@ -467,7 +517,8 @@ typedef struct hop_stats {
     int64_t misses;         /* HOP_LEARNED_RADIUS: particles searched again      */
     int64_t redo_buckets;   /* HOP_LEARNED_RADIUS: buckets of the fallback pass  */
     int64_t premerged;      /* hop_stitch with premerge: row pairs that joined
-                               two chains inside a subvolume                     */
+                               two chains inside a subvolume; hop_subhalos:
+                               symmetric chain boundaries                        */
 } hop_stats;
 
 /* Profiling bits (default 0): 1 = time the sort/tree and kNN stages of

@@ -120,6 +120,8 @@ def load():
     L.hop_halo_stats.argtypes = [vp, i64, vp, vp, vp, i32, vp, C.POINTER(_Params), vp, vp, vp, vp]
     L.hop_stitch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(_Params), i32, i64, vp,
                              vp, vp, vp, vp, C.POINTER(i32), C.POINTER(i32), vp, vp]
+    L.hop_subhalos.argtypes = [vp, i64, vp, vp, vp, i32, vp, C.POINTER(_Params), i32, vp,
+                               C.c_double, vp, vp, vp, vp]
     L.hop_run_batch.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(_Params), vp, vp, vp, vp, vp,
                                 vp, vp, vp, vp, vp, vp]
     f32 = C.c_float
@@ -286,7 +288,7 @@ class HopContext:
         return out
 
     def stitch(self, offsets, index, padded, batch, n, params: HopParams | None = None,
-               premerge=False, stream=None):
+               premerge=False, task_densities=False, stream=None):
         """hop_stitch: whole-box chains and halos from the rows of a batched
         run (batch = run_batch() output; offsets host, index/padded per row).
         Returns device box arrays and the group table."""
@@ -306,7 +308,8 @@ class HopContext:
         self._check(self.lib.hop_stitch(self.h, off.size - 1, off.ctypes.data_as(C.c_void_p),
                                         _ptr(idx_d), _ptr(pad_d), _ptr(batch["density"]),
                                         _ptr(batch["nbr"]), _ptr(batch["hop"]), C.byref(cp),
-                                        int(bool(premerge)), int(n), _ptr(out["density"]),
+                                        (1 if premerge else 0) | (2 if task_densities else 0),
+                                        int(n), _ptr(out["density"]),
                                         _ptr(out["hop"]), _ptr(out["root"]), _ptr(out["chain_of"]),
                                         _ptr(out["group"]), C.byref(nc), C.byref(ng), _ptr(table),
                                         self._stream(stream)))
@@ -339,6 +342,34 @@ class HopContext:
         if vbulk is not None:
             out["vbulk"] = vbulk[:ng]
         return out
+
+    def subhalos(self, nbr, dens, chain_of, n_chains, levels, params: HopParams | None = None,
+                 alpha=0.0, ids=None, stream=None):
+        """hop_subhalos: structure numbers per level [L][n] (device), host
+        table offsets [L+1], and the device table [count, peak, parent,
+        peak density] per structure."""
+        import numpy as np
+        torch = self._torch
+        p = params or HopParams()
+        lv = np.ascontiguousarray(np.asarray(levels, dtype=np.float64))
+        L = lv.size
+        n = nbr.shape[0]
+        sub = torch.empty((L, n), dtype=torch.int32, device=nbr.device)
+        t_off = np.zeros(L + 1, np.int64)
+        table = torch.empty((max(L * n_chains, 1), 3), dtype=torch.int64, device=nbr.device)
+        cp = p.c()
+        ids_d = self._dev(ids, torch.int64)
+        self._check(self.lib.hop_subhalos(self.h, n, _ptr(nbr), _ptr(dens), _ptr(chain_of),
+                                          int(n_chains), _ptr(ids_d), C.byref(cp), L,
+                                          lv.ctypes.data_as(C.c_void_p), float(alpha), _ptr(sub),
+                                          t_off.ctypes.data_as(C.c_void_p), _ptr(table),
+                                          self._stream(stream)))
+        g = int(t_off[-1])
+        t = table[:g]
+        return {"sub": sub, "t_off": t_off.tolist(), "count": t[:, 0].clone(),
+                "peak": (t[:, 1] & 0xFFFFFFFF).to(torch.int32),
+                "parent": (t[:, 1] >> 32).to(torch.int32),
+                "peak_dens": t[:, 2].contiguous().view(torch.float64)}
 
     def sync(self, stream=None):
         self._check(self.lib.hop_sync(self.h, self._stream(stream)))

@@ -615,3 +615,309 @@ int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *de
     *n_groups = (int32_t)G;
     return HOP_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Subhalos (the ADAPTAHOP-style extension of the paper's section 6): chain
+// boundaries kept by direction, symmetric ones only, and at each level the
+// structures of chains joined at or above it.  The boundary hash and the
+// union-find are those of the merge above.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// directed boundary maxima per chain pair: up = lo -> hi, down = hi -> lo
+// (densities are positive, so a maximum of 0 means no pair)
+__global__ void k_dir_insert(int64_t n, const int32_t *__restrict__ nbr, int k_store, int n_merge,
+                             const double *__restrict__ dens, const int32_t *__restrict__ chain_of,
+                             int32_t C, uint64_t *__restrict__ hkeys,
+                             unsigned long long *__restrict__ hup,
+                             unsigned long long *__restrict__ hdown, uint64_t mask, int log2cap,
+                             uint32_t *__restrict__ dflags)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t ci = chain_of[i];
+    if (ci < 0 || ci >= C) return;
+    const double di = dens[i];
+    for (int t = 1; t < n_merge; t++) {
+        const int32_t j = nbr[i * k_store + t];
+        if (j < 0 || j >= n) {
+            atomicOr(dflags, DERR_INDEX);
+            continue;
+        }
+        const int32_t cj = chain_of[j];
+        if (cj < 0 || cj >= C || cj == ci) continue;
+        const double sv = (di + dens[j]) * 0.5;
+        const unsigned long long sb = (unsigned long long)__double_as_longlong(sv);
+        const uint64_t key = ((uint64_t)(uint32_t)min(ci, cj) << 32) | (uint32_t)max(ci, cj);
+        uint64_t slot = log2cap > 0 ? pair_hash(key) >> (64 - log2cap) : 0;
+        bool done = false;
+        for (uint64_t probe = 0; probe <= mask; probe++) {
+            uint64_t k = hkeys[slot];
+            if (k == kEmpty) {
+                k = atomicCAS((unsigned long long *)&hkeys[slot], (unsigned long long)kEmpty,
+                              (unsigned long long)key);
+                if (k == kEmpty) k = key;
+            }
+            if (k == key) {
+                atomicMax(ci < cj ? &hup[slot] : &hdown[slot], sb);
+                done = true;
+                break;
+            }
+            slot = (slot + 1) & mask;
+        }
+        if (!done) atomicOr(dflags, DERR_CAPACITY);
+    }
+}
+
+// symmetric boundaries: both directions present; density the smaller maximum
+__global__ void k_sym_compact(int64_t cap, const uint64_t *__restrict__ hkeys,
+                              const unsigned long long *__restrict__ hup,
+                              const unsigned long long *__restrict__ hdown,
+                              int32_t *__restrict__ elo, int32_t *__restrict__ ehi,
+                              double *__restrict__ es, uint32_t *__restrict__ count)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cap) return;
+    const uint64_t k = hkeys[t];
+    if (k == kEmpty || hup[t] == 0ull || hdown[t] == 0ull) return;
+    const uint32_t at = atomicAdd(count, 1u);
+    elo[at] = (int32_t)(k >> 32);
+    ehi[at] = (int32_t)(k & 0xffffffffu);
+    es[at] = __longlong_as_double((long long)min(hup[t], hdown[t]));
+}
+
+__global__ void k_union_level(int64_t E, const int32_t *__restrict__ elo,
+                              const int32_t *__restrict__ ehi, const double *__restrict__ es,
+                              double level, int32_t *__restrict__ hp)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    if (es[e] >= level) uf_union(hp, elo[e], ehi[e]);
+}
+
+// members (chained, density >= level): count and densest per structure
+__global__ void k_sub_accum(int64_t n, const int32_t *__restrict__ chain_of, int32_t C,
+                            const double *__restrict__ dens, double level,
+                            const int32_t *__restrict__ hp, uint32_t *__restrict__ hcount,
+                            unsigned long long *__restrict__ hpeak)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = chain_of[i];
+    if (c < 0 || c >= C || !(dens[i] >= level)) return;
+    const int32_t h = hp[c];
+    atomicAdd(&hcount[h], 1u);
+    atomicMax(&hpeak[h], (unsigned long long)__double_as_longlong(dens[i]));
+}
+
+__global__ void k_sub_peak_tk(int64_t n, const int32_t *__restrict__ chain_of, int32_t C,
+                              const double *__restrict__ dens, double level,
+                              const int32_t *__restrict__ hp,
+                              const unsigned long long *__restrict__ hpeak,
+                              const int32_t *__restrict__ tk, uint32_t *__restrict__ hptk)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = chain_of[i];
+    if (c < 0 || c >= C || !(dens[i] >= level)) return;
+    const int32_t h = hp[c];
+    if ((unsigned long long)__double_as_longlong(dens[i]) != hpeak[h]) return;
+    atomicMin(&hptk[h], (uint32_t)(tk ? tk[i] : (int32_t)i));
+}
+
+// structures with a member that pass the peak test -> list (key = peak tie key)
+__global__ void k_sub_list(int32_t C, const int32_t *__restrict__ hp,
+                           const uint32_t *__restrict__ hcount,
+                           const unsigned long long *__restrict__ hpeak,
+                           const uint32_t *__restrict__ hptk, double level, double alpha,
+                           uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                           uint32_t *__restrict__ counter)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    if (hp[c] != (int32_t)c || hcount[c] == 0) return;
+    const double pk = __longlong_as_double((long long)hpeak[c]);
+    if (!(pk >= level * (1.0 + alpha / __builtin_sqrt((double)hcount[c])))) return;
+    const uint32_t at = atomicAdd(counter, 1u);
+    keys[at] = hptk[c];
+    vals[at] = (uint32_t)c;
+}
+
+__global__ void k_sub_number(int64_t G, const uint32_t *__restrict__ vals,
+                             const uint32_t *__restrict__ hcount,
+                             const unsigned long long *__restrict__ hpeak,
+                             const uint32_t *__restrict__ hptk, const int32_t *__restrict__ tk2j,
+                             const int32_t *__restrict__ prev, int32_t *__restrict__ num,
+                             hop_subhalo_info *__restrict__ out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= G) return;
+    const uint32_t h = vals[t];
+    num[h] = (int32_t)t;
+    if (out) {
+        hop_subhalo_info g;
+        g.count = hcount[h];
+        const uint32_t ptk = hptk[h];
+        g.peak = tk2j ? tk2j[ptk] : (int32_t)ptk;
+        g.parent = prev ? prev[g.peak] : -1;
+        g.peak_density = __longlong_as_double((long long)hpeak[h]);
+        out[t] = g;
+    }
+}
+
+__global__ void k_sub_label(int64_t n, const int32_t *__restrict__ chain_of, int32_t C,
+                            const double *__restrict__ dens, double level,
+                            const int32_t *__restrict__ hp, const int32_t *__restrict__ num,
+                            int32_t *__restrict__ sub)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = chain_of[i];
+    int32_t lab = -1;
+    if (c >= 0 && c < C && dens[i] >= level) lab = num[hp[c]];
+    sub[i] = lab;
+}
+
+}  // namespace
+
+extern "C" int hop_subhalos(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *density,
+                            const int32_t *chain_of, int32_t n_chains, const int64_t *id,
+                            const hop_params *p, int32_t n_levels, const double *levels,
+                            double alpha, int32_t *sub, int64_t *t_off, hop_subhalo_info *table,
+                            void *stream)
+{
+    if (!ctx) return HOP_ERR_ARG;
+    ctx->err.clear();
+    HOPTRY(hop_check_params(ctx, n, p));
+    if (!nbr || !density || !chain_of || !sub || !t_off || !levels)
+        return hop_fail(ctx, HOP_ERR_ARG, "nbr, density, chain_of, levels, sub and t_off must be non-NULL");
+    if (n_chains < 0 || n_chains > n) return hop_fail(ctx, HOP_ERR_ARG, "n_chains outside [0, n]");
+    if (n_levels < 1 || n_levels > 64) return hop_fail(ctx, HOP_ERR_ARG, "need 1 <= n_levels <= 64");
+    if (!(alpha >= 0) || !(alpha < 1e300)) return hop_fail(ctx, HOP_ERR_ARG, "alpha must be finite and >= 0");
+    for (int l = 0; l < n_levels; l++) {
+        if (!(levels[l] >= 0) || !(levels[l] < 1e300))
+            return hop_fail(ctx, HOP_ERR_ARG, "levels must be finite and >= 0");
+        if (l > 0 && !(levels[l] > levels[l - 1])) return hop_fail(ctx, HOP_ERR_ARG, "levels must ascend");
+    }
+    HOPTRY(hop_set_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *dflags = (uint32_t *)ctx->flags.ptr;
+    uint32_t *dcnt = dflags + 4;
+    const int32_t C = n_chains;
+    const int32_t *tk = nullptr, *tk2j = nullptr;
+    if (id) {
+        HOPTRY(hop_build_tiekeys(ctx, n, id, s));
+        tk = (const int32_t *)ctx->tk.ptr;
+        tk2j = (const int32_t *)ctx->tk2j.ptr;
+    }
+    if (C == 0) {
+        for (int l = 0; l <= n_levels; l++) t_off[l] = 0;
+        k_fill_i32<<<hop_grid(n * n_levels, 256), 256, 0, s>>>(sub, n * n_levels, -1);
+        HOPCHK(ctx, hipGetLastError());
+        return hop_check_device(ctx, s, "hop_subhalos");
+    }
+
+    // 1. directed boundary maxima, then the symmetric ones
+    const int64_t pairs_max = (int64_t)(p->n_merge - 1) * n;
+    int64_t cap = ctx->tuning.hash_slots > 0
+                      ? pow2ceil(ctx->tuning.hash_slots)
+                      : pow2ceil(std::max<int64_t>(4096, std::min<int64_t>(16 * (int64_t)C, 2 * pairs_max + 1)));
+    const int64_t cap_max = pow2ceil(2 * pairs_max + 1);
+    for (;;) {
+        int log2cap = 0;
+        while (((int64_t)1 << log2cap) < cap) log2cap++;
+        HOPTRY(hop_reserve(ctx, ctx->hash_keys, (size_t)cap * 8));
+        HOPTRY(hop_reserve(ctx, ctx->hash_vals, (size_t)cap * 16));
+        uint64_t *hk = (uint64_t *)ctx->hash_keys.ptr;
+        unsigned long long *hup = (unsigned long long *)ctx->hash_vals.ptr;
+        unsigned long long *hdown = hup + cap;
+        HOPCHK(ctx, hipMemsetAsync(hk, 0xff, (size_t)cap * 8, s));
+        HOPCHK(ctx, hipMemsetAsync(hup, 0, (size_t)cap * 16, s));
+        k_dir_insert<<<hop_grid(n, 256), 256, 0, s>>>(n, nbr, p->k_store, p->n_merge, density, chain_of, C,
+                                                      hk, hup, hdown, (uint64_t)(cap - 1), log2cap, dflags);
+        HOPCHK(ctx, hipGetLastError());
+        HOPCHK(ctx, hipMemcpyAsync(ctx->hflags + 2, dflags, 4, hipMemcpyDeviceToHost, s));
+        HOPCHK(ctx, hipStreamSynchronize(s));
+        const uint32_t fl = (uint32_t)ctx->hflags[2];
+        if ((fl & DERR_CAPACITY) && cap < cap_max) {
+            ctx->hflags[3] = (int64_t)(fl & ~DERR_CAPACITY);
+            HOPCHK(ctx, hipMemcpyAsync(dflags, &ctx->hflags[3], 4, hipMemcpyHostToDevice, s));
+            cap *= 2;
+            continue;
+        }
+        break;
+    }
+    HOPTRY(hop_reserve(ctx, ctx->edges_lo, (size_t)cap * 4));
+    HOPTRY(hop_reserve(ctx, ctx->edges_hi, (size_t)cap * 4));
+    HOPTRY(hop_reserve(ctx, ctx->edges_s, (size_t)cap * 8));
+    int32_t *elo = (int32_t *)ctx->edges_lo.ptr;
+    int32_t *ehi = (int32_t *)ctx->edges_hi.ptr;
+    double *es = (double *)ctx->edges_s.ptr;
+    {
+        const uint64_t *hk = (const uint64_t *)ctx->hash_keys.ptr;
+        const unsigned long long *hup = (const unsigned long long *)ctx->hash_vals.ptr;
+        HOPCHK(ctx, hipMemsetAsync(dcnt, 0, 4, s));
+        k_sym_compact<<<hop_grid(cap, 256), 256, 0, s>>>(cap, hk, hup, hup + cap, elo, ehi, es, dcnt);
+        HOPCHK(ctx, hipGetLastError());
+        HOPCHK(ctx, hipMemcpyAsync(ctx->hflags + 2, dcnt, 4, hipMemcpyDeviceToHost, s));
+        HOPCHK(ctx, hipStreamSynchronize(s));
+    }
+    const int64_t E = (int64_t)(uint32_t)ctx->hflags[2];
+
+    // 2. every level
+    const int64_t C1 = (int64_t)C + 1;
+    HOPTRY(hop_reserve(ctx, ctx->work_b, (size_t)C1 * (4 + 4 + 8 + 4 + 4) + 8 * 256));
+    Carver cv{(char *)ctx->work_b.ptr};
+    int32_t *hp = cv.take<int32_t>(C1);
+    uint32_t *hcount = cv.take<uint32_t>(C1);
+    unsigned long long *hpeak = cv.take<unsigned long long>(C1);
+    uint32_t *hptk = cv.take<uint32_t>(C1);
+    int32_t *num = cv.take<int32_t>(C1);
+    HOPTRY(hop_reserve(ctx, ctx->keys_a, (size_t)C * 8));
+    HOPTRY(hop_reserve(ctx, ctx->keys_b, (size_t)C * 8));
+    HOPTRY(hop_reserve(ctx, ctx->vals_a, (size_t)C * 4));
+    HOPTRY(hop_reserve(ctx, ctx->vals_b, (size_t)C * 4));
+    uint64_t *keys = (uint64_t *)ctx->keys_a.ptr;
+    uint32_t *vals = (uint32_t *)ctx->vals_a.ptr;
+    uint64_t *tkeys = (uint64_t *)ctx->keys_b.ptr;
+    uint32_t *tvals = (uint32_t *)ctx->vals_b.ptr;
+    int64_t base = 0;
+    for (int l = 0; l < n_levels; l++) {
+        const double lev = levels[l];
+        k_iota<<<hop_grid(C, 256), 256, 0, s>>>(C, hp);
+        if (E > 0) k_union_level<<<hop_grid(E, 256), 256, 0, s>>>(E, elo, ehi, es, lev, hp);
+        k_compress<<<hop_grid(C, 256), 256, 0, s>>>(C, hp);
+        HOPCHK(ctx, hipMemsetAsync(hcount, 0, (size_t)C * 4, s));
+        HOPCHK(ctx, hipMemsetAsync(hpeak, 0, (size_t)C * 8, s));
+        HOPCHK(ctx, hipMemsetAsync(hptk, 0xff, (size_t)C * 4, s));
+        k_sub_accum<<<hop_grid(n, 256), 256, 0, s>>>(n, chain_of, C, density, lev, hp, hcount, hpeak);
+        k_sub_peak_tk<<<hop_grid(n, 256), 256, 0, s>>>(n, chain_of, C, density, lev, hp, hpeak, tk, hptk);
+        HOPCHK(ctx, hipMemsetAsync(dcnt + 2, 0, 4, s));
+        k_sub_list<<<hop_grid(C, 256), 256, 0, s>>>(C, hp, hcount, hpeak, hptk, lev, alpha, keys, vals,
+                                                    dcnt + 2);
+        HOPCHK(ctx, hipGetLastError());
+        HOPCHK(ctx, hipMemcpyAsync(&ctx->hflags[6], dcnt + 2, 4, hipMemcpyDeviceToHost, s));
+        HOPCHK(ctx, hipStreamSynchronize(s));
+        const int64_t G = (int64_t)(uint32_t)ctx->hflags[6];
+        if (G > 1) {
+            HOPTRY(hop_radix_sort(ctx, keys, vals, tkeys, tvals, G, 32, s));
+            k_key_peak<<<hop_grid(G, 256), 256, 0, s>>>(G, vals, hpeak, keys);
+            HOPTRY(hop_radix_sort(ctx, keys, vals, tkeys, tvals, G, 64, s));
+            k_key_count<<<hop_grid(G, 256), 256, 0, s>>>(G, vals, hcount, keys);
+            HOPTRY(hop_radix_sort(ctx, keys, vals, tkeys, tvals, G, 32, s));
+        }
+        int32_t *sub_l = sub + (int64_t)l * n;
+        if (G > 0)
+            k_sub_number<<<hop_grid(G, 256), 256, 0, s>>>(G, vals, hcount, hpeak, hptk, tk2j,
+                                                          l > 0 ? sub_l - n : nullptr, num,
+                                                          table ? table + base : nullptr);
+        k_sub_label<<<hop_grid(n, 256), 256, 0, s>>>(n, chain_of, C, density, lev, hp, num, sub_l);
+        HOPCHK(ctx, hipGetLastError());
+        t_off[l] = base;
+        base += G;
+    }
+    t_off[n_levels] = base;
+    ctx->stats.premerged = E;
+    return hop_check_device(ctx, s, "hop_subhalos");
+}

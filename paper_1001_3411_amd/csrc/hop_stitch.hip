@@ -66,22 +66,39 @@ __global__ void k_owner_missing(int64_t n, const int32_t *__restrict__ owner,
     if (g < n && owner[g] < 0) atomicOr(dflags, DERR_OWNER);
 }
 
+// Density of every row: its own (as its subvolume computed it), or its
+// owner's (the annulus exchange carrying densities as well as chains).
+// tk = box index of the row, the tie key of links and of the group order.
+__global__ void k_row_dens(int64_t rows, const int64_t *__restrict__ index, int64_t n,
+                           const int32_t *__restrict__ owner, const double *__restrict__ density_b,
+                           int own_density, double *__restrict__ dens, int32_t *__restrict__ tk)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const int64_t g = index[r];
+    const bool ok = g >= 0 && g < n;
+    tk[r] = ok ? (int32_t)g : 0;
+    dens[r] = (own_density && ok) ? density_b[owner[g]] : density_b[r];
+}
+
 // Links over rows: a local row to its link (a row of its subvolume), a
 // padded row to its owner's row (the virtual link).  lroot gets the links
 // without virtual links (padded rows stay self-linked), for the premerge.
-// tk = box index of the row, the tie key of the merge's group order.
+// The link of a local row is hop_b's, or (hop_b NULL) formed again from
+// its first n_hop list entries with the row densities dens: the densest,
+// equal densities to the smaller box index (as in the whole box).
 __global__ void k_row_links(int64_t rows, const int64_t *__restrict__ off, int n_sub,
                             const int64_t *__restrict__ index, const uint8_t *__restrict__ padded,
-                            const int32_t *__restrict__ hop_b, int64_t n,
+                            const int32_t *__restrict__ hop_b, const int32_t *__restrict__ nbr_b,
+                            int k_store, int n_hop, const double *__restrict__ dens,
+                            const int32_t *__restrict__ tk, int64_t n,
                             const int32_t *__restrict__ owner, int32_t *__restrict__ vroot,
-                            int32_t *__restrict__ lroot, int32_t *__restrict__ tk,
-                            uint32_t *__restrict__ dflags)
+                            int32_t *__restrict__ lroot, uint32_t *__restrict__ dflags)
 {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rows) return;
     const int64_t g = index[r];
     const bool pad = padded && padded[r];
-    tk[r] = (g >= 0 && g < n) ? (int32_t)g : 0;
     int32_t own = (int32_t)r;
     if (g >= 0 && g < n && owner[g] >= 0) own = owner[g];
     if (pad) {
@@ -91,10 +108,30 @@ __global__ void k_row_links(int64_t rows, const int64_t *__restrict__ off, int n
     }
     const int sv = sub_of_row(off, n_sub, r);
     const int64_t base = off[sv], cnt = off[sv + 1] - base;
-    const int32_t h = hop_b[r];
     int32_t to = (int32_t)r;
-    if (h >= 0 && h < cnt) to = (int32_t)(base + h);
-    else atomicOr(dflags, DERR_INDEX);
+    if (hop_b) {
+        const int32_t h = hop_b[r];
+        if (h >= 0 && h < cnt) to = (int32_t)(base + h);
+        else atomicOr(dflags, DERR_INDEX);
+    } else {
+        double bd = dens[r];
+        int32_t bt = tk[r];
+        for (int t = 0; t < n_hop; t++) {
+            const int32_t j = nbr_b[r * k_store + t];
+            if (j < 0 || j >= cnt) {
+                atomicOr(dflags, DERR_INDEX);
+                continue;
+            }
+            const int32_t J = (int32_t)(base + j);
+            const double dj = dens[J];
+            const int32_t tj = tk[J];
+            if (dj > bd || (dj == bd && tj < bt)) {
+                to = J;
+                bd = dj;
+                bt = tj;
+            }
+        }
+    }
     vroot[r] = to;
     lroot[r] = to;
 }
@@ -113,10 +150,10 @@ __global__ void k_true_roots(int64_t rows, const int32_t *__restrict__ vroot,
 
 // chain of every row from its owner (the annulus exchange), box outputs of
 // the local rows
-__global__ void k_row_chains(int64_t rows, const int64_t *__restrict__ off, int n_sub,
-                             const int64_t *__restrict__ index, const uint8_t *__restrict__ padded,
-                             const double *__restrict__ dens, const int32_t *__restrict__ hop_b,
-                             int64_t n, const int32_t *__restrict__ owner,
+__global__ void k_row_chains(int64_t rows, const int64_t *__restrict__ index,
+                             const uint8_t *__restrict__ padded, const double *__restrict__ dens,
+                             const int32_t *__restrict__ lnk, int64_t n,
+                             const int32_t *__restrict__ owner,
                              const int32_t *__restrict__ vroot, const uint32_t *__restrict__ num,
                              double delta_outer, int32_t *__restrict__ label,
                              double *__restrict__ density, int32_t *__restrict__ hop,
@@ -138,11 +175,8 @@ __global__ void k_row_chains(int64_t rows, const int64_t *__restrict__ off, int 
     }
     label[r] = c;
     if (padded && padded[r]) return;
-    const int sv = sub_of_row(off, n_sub, r);
-    const int64_t base = off[sv], cnt = off[sv + 1] - base;
-    const int32_t h = hop_b[r];
     density[g] = dens[r];
-    if (hop) hop[g] = (h >= 0 && h < cnt) ? (int32_t)index[base + h] : (int32_t)g;
+    if (hop) hop[g] = (int32_t)index[lnk[r]];
     root[g] = (int32_t)groot;
     chain_of[g] = c;
 }
@@ -229,7 +263,7 @@ struct Carve {
 
 extern "C" int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, const int64_t *index,
                           const uint8_t *padded, const double *density_b, const int32_t *nbr_b,
-                          const int32_t *hop_b, const hop_params *p, int32_t premerge, int64_t n,
+                          const int32_t *hop_b, const hop_params *p, int32_t mode, int64_t n,
                           double *density, int32_t *hop, int32_t *root, int32_t *chain_of,
                           int32_t *group, int32_t *n_chains, int32_t *n_groups,
                           hop_group_info *groups, void *stream)
@@ -246,9 +280,14 @@ extern "C" int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, c
         return hop_fail(ctx, HOP_ERR_ARG, "need n <= rows < 2^31");
     if (!(p->flags & HOP_PADDED_RULES) || !padded)
         return hop_fail(ctx, HOP_ERR_ARG, "stitching needs the padded rules and the padding flags");
-    if (!index || !density_b || !nbr_b || !hop_b || !density || !root || !chain_of || !group ||
-        !n_chains || !n_groups)
+    if (!index || !density_b || !nbr_b || !density || !root || !chain_of || !group || !n_chains ||
+        !n_groups)
         return hop_fail(ctx, HOP_ERR_ARG, "index, batch outputs and box outputs must be non-NULL");
+    if (mode & ~(HOP_STITCH_PREMERGE | HOP_STITCH_TASK_DENSITIES))
+        return hop_fail(ctx, HOP_ERR_ARG, "unknown stitch mode bit");
+    const bool task_dens = (mode & HOP_STITCH_TASK_DENSITIES) != 0;
+    const bool premerge = (mode & HOP_STITCH_PREMERGE) != 0;
+    if (task_dens && !hop_b) return hop_fail(ctx, HOP_ERR_ARG, "HOP_STITCH_TASK_DENSITIES needs hop_b");
     HOPTRY(hop_set_device(ctx));
     hipStream_t s = (hipStream_t)stream;
     uint32_t *dflags = (uint32_t *)ctx->flags.ptr;
@@ -256,13 +295,15 @@ extern "C" int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, c
 
     // scratch: offsets, owner rows, links, labels, tie keys, lists, premerge pairs
     const int64_t pre_cap = rows * (int64_t)(nm > 1 ? nm - 1 : 1);
-    const size_t need = (size_t)(n_sub + 1) * 8 + (size_t)n * 8 + (size_t)rows * (4 * 5 + 4 * nm) +
+    const size_t need = (size_t)(n_sub + 1) * 8 + (size_t)n * 8 + (size_t)rows * (8 + 4 * 6 + 4 * nm) +
                         (size_t)pre_cap * 8 + 16 * 256;
     HOPTRY(hop_reserve(ctx, ctx->stitch, need));
     Carve cv{(char *)ctx->stitch.ptr};
     int64_t *off = cv.take<int64_t>(n_sub + 1);
     int32_t *owner = cv.take<int32_t>(n);
     uint32_t *flag = cv.take<uint32_t>(n);
+    double *dens = cv.take<double>(rows);
+    int32_t *lnk = cv.take<int32_t>(rows);
     int32_t *vroot = cv.take<int32_t>(rows);
     int32_t *lroot = cv.take<int32_t>(rows);
     int32_t *label = cv.take<int32_t>(rows);
@@ -280,16 +321,22 @@ extern "C" int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, c
     HOPCHK(ctx, hipGetLastError());
     HOPTRY(hop_check_device(ctx, s, "hop_stitch"));  // also keeps `offsets` until the copy ran
 
-    // 2. links and virtual links over rows, resolved to the true peaks
-    k_row_links<<<hop_grid(rows, 256), 256, 0, s>>>(rows, off, n_sub, index, padded, hop_b, n, owner,
-                                                    vroot, lroot, tk, dflags);
+    // 2. row densities; links and virtual links over rows, resolved to the
+    //    true peaks
+    k_row_dens<<<hop_grid(rows, 256), 256, 0, s>>>(rows, index, n, owner, density_b, task_dens ? 0 : 1,
+                                                   dens, tk);
+    k_row_links<<<hop_grid(rows, 256), 256, 0, s>>>(rows, off, n_sub, index, padded,
+                                                    task_dens ? hop_b : nullptr, nbr_b, p->k_store,
+                                                    p->n_hop, dens, tk, n, owner, vroot, lroot,
+                                                    dflags);
     HOPCHK(ctx, hipGetLastError());
+    HOPCHK(ctx, hipMemcpyAsync(lnk, vroot, (size_t)rows * 4, hipMemcpyDeviceToDevice, s));
     HOPTRY(hop_jump_impl(ctx, rows, vroot, s));
     if (premerge) HOPTRY(hop_jump_impl(ctx, rows, lroot, s));
 
     // 3. chains: alive true peaks numbered by box index
     HOPCHK(ctx, hipMemsetAsync(flag, 0, (size_t)n * 4, s));
-    k_true_roots<<<hop_grid(rows, 256), 256, 0, s>>>(rows, vroot, index, density_b, p->delta_outer, n,
+    k_true_roots<<<hop_grid(rows, 256), 256, 0, s>>>(rows, vroot, index, dens, p->delta_outer, n,
                                                      flag);
     HOPCHK(ctx, hipGetLastError());
     uint32_t *total = dflags + 2;
@@ -297,9 +344,9 @@ extern "C" int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, c
     HOPCHK(ctx, hipMemcpyAsync(ctx->hflags, total, 4, hipMemcpyDeviceToHost, s));
 
     // 4. every row's chain from its owner; box outputs of the local rows
-    k_row_chains<<<hop_grid(rows, 256), 256, 0, s>>>(rows, off, n_sub, index, padded, density_b, hop_b,
-                                                     n, owner, vroot, flag, p->delta_outer, label,
-                                                     density, hop, root, chain_of);
+    k_row_chains<<<hop_grid(rows, 256), 256, 0, s>>>(rows, index, padded, dens, lnk, n, owner, vroot,
+                                                     flag, p->delta_outer, label, density, hop, root,
+                                                     chain_of);
     k_row_lists<<<hop_grid(rows, 256), 256, 0, s>>>(rows, off, n_sub, nbr_b, p->k_store, nm, nbrm,
                                                     dflags);
     HOPCHK(ctx, hipGetLastError());
@@ -312,7 +359,7 @@ extern "C" int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, c
     if (premerge && C > 0) {
         uint32_t *cnt = dflags + 12;
         HOPCHK(ctx, hipMemsetAsync(cnt, 0, 4, s));
-        k_premerge<<<hop_grid(rows, 256), 256, 0, s>>>(rows, nbrm, nm, density_b, padded, lroot, label,
+        k_premerge<<<hop_grid(rows, 256), 256, 0, s>>>(rows, nbrm, nm, dens, padded, lroot, label,
                                                        p->delta_outer, p->delta_saddle, p->delta_peak,
                                                        pre_lo, pre_hi, cnt, pre_cap);
         HOPCHK(ctx, hipGetLastError());
@@ -328,7 +375,7 @@ extern "C" int hop_stitch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, c
     hop_params q = *p;
     q.k_store = nm;
     int32_t ng = 0;
-    HOPTRY(hop_merge_impl(ctx, rows, nbrm, density_b, vroot, label, C, tk, padded, &q, group_r, &ng,
+    HOPTRY(hop_merge_impl(ctx, rows, nbrm, dens, vroot, label, C, tk, padded, &q, group_r, &ng,
                           groups, mx, s));
     k_box_groups<<<hop_grid(rows, 256), 256, 0, s>>>(rows, index, padded, n, group_r, group);
     HOPCHK(ctx, hipGetLastError());

@@ -68,7 +68,7 @@ def test_padded_subvolumes_reproduce_box_densities(ctx, box2):
     assert checked > 0.9 * p.n
 
 
-def _stitched(ctx, p, premerge):
+def _stitched(ctx, p, premerge, task_densities=False):
     import time
 
     import torch
@@ -86,10 +86,11 @@ def _stitched(ctx, p, premerge):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b = ctx.run_batch(pos_b, d.offsets, sub, padded=pad_b, mean_density=md)
-        out = ctx.stitch(d.offsets, idx_b, pad_b, b, p.n, box, premerge=premerge)
+        out = ctx.stitch(d.offsets, idx_b, pad_b, b, p.n, box, premerge=premerge,
+                         task_densities=task_densities)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-    print(f"[stitch] premerge={premerge}: {p.n} particles, 8 subvolumes "
+    print(f"[stitch] premerge={premerge} task_densities={task_densities}: {p.n} particles, 8 subvolumes "
           f"({d.pos.shape[0]} rows with padding): {dt * 1e3:.1f} ms; {out['n_chains']} chains, "
           f"{out['n_groups']} groups, {ctx.stats()['premerged']} premerged pairs", flush=True)
     return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
@@ -122,3 +123,20 @@ def test_stitched_with_premerge(ctx, box2):
     print(f"[stitch] premerge group change fraction {chg:.3e} "
           f"({g['n_groups']} vs {r.n_groups} groups)", flush=True)
     assert chg < 1e-3
+
+
+def test_stitched_with_task_densities(ctx, box2):
+    """The paper's own form: padded particles keep the densities their
+    subvolume gave them and local links are the subvolume's.  A padded
+    particle whose list the padding cut short can then carry a wrong density
+    into a local particle's link or a boundary; the chains are still rebuilt
+    and merged, and the fractions of changed links and groups are reported."""
+    from paper_1001_3411_amd.report import group_change_fraction
+    p, r = box2
+    g = _stitched(ctx, p, premerge=False, task_densities=True)
+    assert np.array_equal(g["density"], r.density)
+    link_chg = float(np.mean(g["hop"] != r.hop))
+    chg = group_change_fraction(r.group, g["group"])
+    print(f"[stitch] task densities: link change fraction {link_chg:.3e}, group change "
+          f"fraction {chg:.3e} ({g['n_groups']} vs {r.n_groups} groups)", flush=True)
+    assert link_chg < 1e-3 and chg < 1e-2
