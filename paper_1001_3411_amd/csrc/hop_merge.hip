@@ -886,6 +886,7 @@ extern "C" int hop_subhalos(hop_ctx *ctx, int64_t n, const int32_t *nbr, const d
     for (int l = 0; l < n_levels; l++) {
         const double lev = levels[l];
         k_iota<<<hop_grid(C, 256), 256, 0, s>>>(C, hp);
+        k_fill_i32<<<hop_grid(C, 256), 256, 0, s>>>(num, C, -1);  // structures not kept: no number
         if (E > 0) k_union_level<<<hop_grid(E, 256), 256, 0, s>>>(E, elo, ehi, es, lev, hp);
         k_compress<<<hop_grid(C, 256), 256, 0, s>>>(C, hp);
         HOPCHK(ctx, hipMemsetAsync(hcount, 0, (size_t)C * 4, s));
