@@ -332,6 +332,27 @@ int hop_halo_stats(hop_ctx *ctx, int64_t n, const uint32_t *pos, const float *ve
                    const hop_params *p, double *com, double *rmax, double *vbulk, void *stream);
 
 /*
+ * hop_halo_stats_noalloc -- hop_halo_stats for callers that cannot allocate
+ * device memory (code being captured into a HIP graph, serving loops,
+ * harnesses that forbid allocation): the same outputs from the same kernels,
+ * with the per-halo sums in a static device array of the library instead of
+ * context memory.  It calls no allocating routine and does not synchronise:
+ * errors on the device (a group number or peak out of range) are reported
+ * by the next synchronising call (hop_sync).
+ *
+ * Limit: n_groups <= HOP_NOALLOC_MAX_GROUPS (else HOP_ERR_ARG); the array
+ * (72 bytes per group, 18 MiB) is held on every GPU the library runs on
+ * until the process ends.  All calls on one GPU share that array and each
+ * clears it first: calls that overlap on one GPU (other streams, other
+ * contexts, other threads) race and give wrong results.
+ */
+#define HOP_NOALLOC_MAX_GROUPS (1 << 18)
+int hop_halo_stats_noalloc(hop_ctx *ctx, int64_t n, const uint32_t *pos, const float *vel,
+                           const int32_t *group, int32_t n_groups, const hop_group_info *groups,
+                           const hop_params *p, double *com, double *rmax, double *vbulk,
+                           void *stream);
+
+/*
  * hop_subhalos -- substructure inside the chains (the ADAPTAHOP-style
  * extension sketched in the paper's subhalo subsection: symmetric
  * boundaries between chains, boundary links below a level delta_s

@@ -118,6 +118,8 @@ def load():
     L.hop_merge.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, C.POINTER(_Params), vp,
                             C.POINTER(i32), vp, vp]
     L.hop_halo_stats.argtypes = [vp, i64, vp, vp, vp, i32, vp, C.POINTER(_Params), vp, vp, vp, vp]
+    L.hop_halo_stats_noalloc.argtypes = [vp, i64, vp, vp, vp, i32, vp, C.POINTER(_Params), vp,
+                                         vp, vp, vp]
     L.hop_stitch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(_Params), i32, i64, vp,
                              vp, vp, vp, vp, C.POINTER(i32), C.POINTER(i32), vp, vp]
     L.hop_subhalos.argtypes = [vp, i64, vp, vp, vp, i32, vp, C.POINTER(_Params), i32, vp,

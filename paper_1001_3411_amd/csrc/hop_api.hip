@@ -139,6 +139,7 @@ int hop_ctx_create(int device, hop_ctx **out)
         else
             (void)hipGetLastError();
     }
+    if (rc == HOP_OK) rc = hop_noalloc_init(ctx);
     if (rc == HOP_OK) rc = hop_reserve(ctx, ctx->flags, 4096);
     if (rc == HOP_OK && hipMemset(ctx->flags.ptr, 0, 4096) != hipSuccess) rc = HOP_ERR_HIP;
     if (rc == HOP_OK && hipHostMalloc((void **)&ctx->hflags, 4096, 0) != hipSuccess) rc = HOP_ERR_NOMEM;

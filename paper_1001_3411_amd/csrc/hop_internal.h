@@ -78,6 +78,9 @@ struct hop_ctx {
     DevBuf srt_nbr, srt_dens;     // density + links: sorted copies of list heads and densities
     DevBuf jump_done;             // chains: particles whose root is final
     DevBuf stitch;                // stitching: owner rows, virtual-link roots, labels
+    // hop_halo_stats_noalloc: this device's address of the static scratch
+    // (set at context creation by hop_noalloc_init)
+    void *noalloc_scratch = nullptr;
     int radius_kind = 0;          // HOP_RADIUS_* of the loaded model, 0 = none
     float radius_margin = 0.0f;
     float radius_occupancy = 8.0f;
@@ -98,6 +101,9 @@ int hop_hip_fail(hop_ctx *ctx, hipError_t e, const char *what);
 int hop_reserve(hop_ctx *ctx, DevBuf &b, size_t bytes);
 int hop_check_params(hop_ctx *ctx, int64_t n, const hop_params *p);
 int hop_set_device(hop_ctx *ctx);
+// Looks up this device's address of the static scratch of
+// hop_halo_stats_noalloc (hop_stats.hip); the context's device is current.
+int hop_noalloc_init(hop_ctx *ctx);
 // Reads the device error bits (synchronising the stream) and turns them into
 // a return code.
 int hop_check_device(hop_ctx *ctx, hipStream_t s, const char *stage);

@@ -13,6 +13,7 @@
 // velocity sums are FP64 atomics: their order, and so their last bits,
 // vary from run to run within the FP64 summation bound.
 #include <algorithm>
+#include <string>
 
 #include "hop_internal.h"
 
@@ -148,13 +149,19 @@ k_stats_radius(int64_t n, const uint32_t *__restrict__ pos, const int32_t *__res
 
 }  // namespace
 
-extern "C" int hop_halo_stats(hop_ctx *ctx, int64_t n, const uint32_t *pos, const float *vel,
-                              const int32_t *group, int32_t n_groups, const hop_group_info *groups,
-                              const hop_params *p, double *com, double *rmax, double *vbulk,
-                              void *stream)
+namespace {
+
+__global__ void k_zero_u64(unsigned long long *__restrict__ p, int64_t n)
 {
-    if (!ctx) return HOP_ERR_ARG;
-    ctx->err.clear();
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0ull;
+}
+
+// Argument checks shared by both entry points.
+int stats_args(hop_ctx *ctx, int64_t n, const uint32_t *pos, const float *vel, const int32_t *group,
+               int32_t n_groups, const hop_group_info *groups, const hop_params *p, double *com,
+               double *rmax, double *vbulk)
+{
     if (!p) return hop_fail(ctx, HOP_ERR_ARG, "params is NULL");
     if (n < 1 || n >= ((int64_t)1 << 31)) return hop_fail(ctx, HOP_ERR_ARG, "need 1 <= n < 2^31");
     if (n_groups < 0) return hop_fail(ctx, HOP_ERR_ARG, "n_groups < 0");
@@ -162,18 +169,21 @@ extern "C" int hop_halo_stats(hop_ctx *ctx, int64_t n, const uint32_t *pos, cons
     if (!pos || !group || (n_groups > 0 && (!groups || !com || !rmax)))
         return hop_fail(ctx, HOP_ERR_ARG, "pos, group, groups, com and rmax must be non-NULL");
     if (vel && !vbulk) return hop_fail(ctx, HOP_ERR_ARG, "vbulk must be non-NULL when vel is given");
-    HOPTRY(hop_set_device(ctx));
-    hipStream_t s = (hipStream_t)stream;
-    if (n_groups == 0) return HOP_OK;
+    return HOP_OK;
+}
+
+// The three passes over scratch osum/vsum/mean (3 n_groups words each),
+// cleared here with fill kernels (no memset nodes, no allocation).
+int stats_launch(hop_ctx *ctx, int64_t n, const uint32_t *pos, const float *vel, const int32_t *group,
+                 int32_t n_groups, const hop_group_info *groups, const hop_params *p, double *com,
+                 double *rmax, double *vbulk, unsigned long long *osum, double *vsum, double *mean,
+                 hipStream_t s)
+{
     const int periodic = (p->flags & HOP_PERIODIC) ? 1 : 0;
     const int64_t G = (int64_t)1 << p->grid_bits;
-    const size_t g3 = (size_t)n_groups * 3;
-    HOPTRY(hop_reserve(ctx, ctx->work_e, g3 * 8 * 3));  // offset sums, velocity sums, mean offsets
-    unsigned long long *osum = (unsigned long long *)ctx->work_e.ptr;
-    double *vsum = (double *)(osum + g3);
-    double *mean = vsum + g3;
-    HOPCHK(ctx, hipMemsetAsync(osum, 0, g3 * 8 * 2, s));
-    HOPCHK(ctx, hipMemsetAsync(rmax, 0, (size_t)n_groups * 8, s));
+    const int64_t g3 = (int64_t)n_groups * 3;
+    k_zero_u64<<<hop_grid(2 * g3, 256), 256, 0, s>>>(osum, 2 * g3);  // osum and vsum are adjacent
+    k_zero_u64<<<hop_grid(n_groups, 256), 256, 0, s>>>((unsigned long long *)rmax, n_groups);
     const int grid = (int)std::min<int64_t>(hop_grid(n, kStatsBlock), (int64_t)ctx->n_cu * 8);
     k_stats_sum<<<grid, kStatsBlock, 0, s>>>(n, pos, vel, group, n_groups, groups, periodic, G, osum,
                                                  vel ? vsum : nullptr, (uint32_t *)ctx->flags.ptr);
@@ -185,5 +195,68 @@ extern "C" int hop_halo_stats(hop_ctx *ctx, int64_t n, const uint32_t *pos, cons
     k_stats_radius<<<grid, kStatsBlock, 0, s>>>(n, pos, group, n_groups, groups, periodic, G, mean,
                                                     (unsigned long long *)rmax);
     HOPCHK(ctx, hipGetLastError());
+    return HOP_OK;
+}
+
+// Scratch of hop_halo_stats_noalloc: 9 words per group (offset sums,
+// velocity sums, mean offsets), for up to HOP_NOALLOC_MAX_GROUPS groups.
+// Each GPU the library runs on holds its own copy until the process ends;
+// host code uses the address hipGetSymbolAddress gives on that device
+// (hop_ctx.noalloc_scratch), never the array's name.
+static __device__ __align__(256) unsigned long long scratch[(size_t)HOP_NOALLOC_MAX_GROUPS * 9];
+
+}  // namespace
+
+int hop_noalloc_init(hop_ctx *ctx)
+{
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return hop_fail(ctx, HOP_ERR_HIP, "hipGetSymbolAddress of the static statistics scratch failed");
+    }
+    ctx->noalloc_scratch = ptr;
+    return HOP_OK;
+}
+
+extern "C" int hop_halo_stats(hop_ctx *ctx, int64_t n, const uint32_t *pos, const float *vel,
+                              const int32_t *group, int32_t n_groups, const hop_group_info *groups,
+                              const hop_params *p, double *com, double *rmax, double *vbulk,
+                              void *stream)
+{
+    if (!ctx) return HOP_ERR_ARG;
+    ctx->err.clear();
+    HOPTRY(stats_args(ctx, n, pos, vel, group, n_groups, groups, p, com, rmax, vbulk));
+    HOPTRY(hop_set_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    if (n_groups == 0) return HOP_OK;
+    const size_t g3 = (size_t)n_groups * 3;
+    HOPTRY(hop_reserve(ctx, ctx->work_e, g3 * 8 * 3));  // offset sums, velocity sums, mean offsets
+    unsigned long long *osum = (unsigned long long *)ctx->work_e.ptr;
+    double *vsum = (double *)(osum + g3);
+    double *mean = vsum + g3;
+    HOPTRY(stats_launch(ctx, n, pos, vel, group, n_groups, groups, p, com, rmax, vbulk, osum, vsum, mean, s));
     return hop_check_device(ctx, s, "hop_halo_stats");
+}
+
+extern "C" int hop_halo_stats_noalloc(hop_ctx *ctx, int64_t n, const uint32_t *pos, const float *vel,
+                                      const int32_t *group, int32_t n_groups,
+                                      const hop_group_info *groups, const hop_params *p, double *com,
+                                      double *rmax, double *vbulk, void *stream)
+{
+    if (!ctx) return HOP_ERR_ARG;
+    ctx->err.clear();
+    HOPTRY(stats_args(ctx, n, pos, vel, group, n_groups, groups, p, com, rmax, vbulk));
+    if (n_groups > HOP_NOALLOC_MAX_GROUPS)
+        return hop_fail(ctx, HOP_ERR_ARG, "n_groups exceeds HOP_NOALLOC_MAX_GROUPS (" +
+                                              std::to_string(HOP_NOALLOC_MAX_GROUPS) + ")");
+    if (!ctx->noalloc_scratch) return hop_fail(ctx, HOP_ERR_HIP, "static scratch not set up");
+    HOPTRY(hop_set_device(ctx));
+    hipStream_t s = (hipStream_t)stream;
+    if (n_groups == 0) return HOP_OK;
+    const size_t g3 = (size_t)n_groups * 3;
+    unsigned long long *osum = (unsigned long long *)ctx->noalloc_scratch;
+    double *vsum = (double *)(osum + g3);
+    double *mean = vsum + g3;
+    return stats_launch(ctx, n, pos, vel, group, n_groups, groups, p, com, rmax, vbulk, osum, vsum, mean, s);
 }
