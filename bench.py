@@ -270,6 +270,17 @@ def bench_box(args):
     log(f"{args.steps} steps: {ms_step:.2f} ms/step, knn {np.mean(knn_ms):.2f} ms, "
         f"sort+tree {np.mean(sort_ms):.2f} ms, groups={groups} chains={chains}")
     roofline = knn_roofline(n, float(np.mean(knn_ms)), "k_knn_density", value, fused=True)
+    # the kNN kernel's work, from its device counters (one untimed run)
+    ctx.set_profiling(3)
+    out = step()
+    st = ctx.stats()
+    ctx.set_profiling(0)
+    buckets = (n + 63) // 64
+    roofline["work"] = {"nodes_per_particle": st["nodes_visited"] / n,
+                        "leaf_batches_per_particle": st["leaves_scanned"] / n / 4,
+                        "insert_iterations_per_bucket": st["insert_iterations"] / buckets,
+                        "offered_per_query": st["offered"] / n}
+    log(f"kNN work: {roofline['work']}")
     # per-halo statistics of the last step's labels (an output after the
     # path, outside the timed step): centre, maximum radius, and the bulk
     # velocity of a seeded synthetic velocity field
@@ -323,6 +334,8 @@ def bench_box(args):
                             "ms_knn": float(np.mean(kms)), "ms_radius": float(np.mean(rms)),
                             "nodes_per_particle": st["nodes_visited"] / n,
                             "leaf_batches_per_particle": st["leaves_scanned"] / n / 4,
+                            "insert_iterations_per_bucket": st["insert_iterations"] / ((n + 63) // 64),
+                            "offered_per_query": st["offered"] / n,
                             "misses": st["misses"], "miss_fraction": st["misses"] / n,
                             "fallback_buckets": st["redo_buckets"], "identical_output": same}
             if name != "plain":

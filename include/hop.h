@@ -66,7 +66,7 @@ extern "C" {
 
 /*
  * Parameters (section 4.1 and Table 2 of the paper).  Constraints:
- *   1 <= n_merge <= n_hop <= k_store <= n_dens <= 64,
+ *   1 <= n_merge <= n_hop <= k_store <= n_dens <= 128,
  *   delta_* finite and >= 0, mean_density > 0 (or 0 for the default),
  *   1 <= grid_bits <= 21.
  * n_dens     particles in the smoothing kernel, self included
@@ -128,8 +128,9 @@ const char *hop_last_error(const hop_ctx *ctx);
  * r_max^2 = d^2 to L_i[n_dens-1], h = r_max/2, and
  *   density[i] = sum_t W(|x_i - x_{L_i[t]}|, h) / mean_density
  * with the M4 cubic spline W (unit masses), summed pairwise over a
- * zero-padded 64-slot array.  The arithmetic is FP64 (round to nearest, no
- * contraction, correctly rounded division and square root).  Under
+ * zero-padded array of 64 slots (128 when n_dens > 64).  The arithmetic
+ * is FP64 (round to nearest, no contraction, correctly rounded division
+ * and square root).  Under
  * HOP_DENSITY_FP32 the same operation sequence runs in FP32 after rounding
  * 4 d^2 and r_max^2 to FP32; the neighbour lists are unchanged (the search
  * is exact either way) and the densities are returned widened to FP64.
@@ -540,11 +541,17 @@ typedef struct hop_stats {
     int64_t premerged;      /* hop_stitch with premerge: row pairs that joined
                                two chains inside a subvolume; hop_subhalos:
                                symmetric chain boundaries                        */
+    int64_t insert_iterations; /* kNN: heap-insertion loop iterations, summed
+                                  over buckets (each runs for all 64 lanes)     */
+    int64_t offered;        /* kNN: candidates offered to a lane's heap (those
+                               within the lane's bound when their batch was
+                               tested; each costs the lane one iteration)        */
 } hop_stats;
 
 /* Profiling bits (default 0): 1 = time the sort/tree and kNN stages of
    hop_density with HIP events (synchronises the stream inside the call);
-   2 = also count tree nodes tested and leaves scanned (device atomics). */
+   2 = also count tree nodes tested, leaves scanned, heap-insertion loop
+   iterations and offered candidates (device atomics). */
 int hop_set_profiling(hop_ctx *ctx, int on);
 int hop_get_stats(const hop_ctx *ctx, hop_stats *out);
 

@@ -54,7 +54,8 @@ class _Stats(C.Structure):
     _fields_ = [("ms_sort", C.c_double), ("ms_knn", C.c_double), ("n", C.c_int64),
                 ("nodes_visited", C.c_int64), ("leaves_scanned", C.c_int64),
                 ("ms_radius", C.c_double), ("misses", C.c_int64), ("redo_buckets", C.c_int64),
-                ("premerged", C.c_int64)]
+                ("premerged", C.c_int64), ("insert_iterations", C.c_int64),
+                ("offered", C.c_int64)]
 
 
 @dataclass

@@ -126,11 +126,11 @@ int hop_check_device(hop_ctx *ctx, hipStream_t s, const char *stage);
 // Exclusive scan of n uint32 values, in place; the total is written to
 // *total_dev (device pointer) when non-null.  Totals must stay below 2^32.
 int hop_scan_u32(hop_ctx *ctx, uint32_t *data, int64_t n, uint32_t *total_dev, hipStream_t s);
-// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
-// keys/vals hold the input and receive the output; tk/tv are scratch of
-// the same sizes.
+// Stable LSD radix sort of (key, value) pairs on key bits [lo_bit, bits)
+// (pairs equal on those bits keep their input order).  keys/vals hold the
+// input and receive the output; tk/tv are scratch of the same sizes.
 int hop_radix_sort(hop_ctx *ctx, uint64_t *keys, uint32_t *vals, uint64_t *tk, uint32_t *tv,
-                   int64_t n, int bits, hipStream_t s);
+                   int64_t n, int bits, hipStream_t s, int lo_bit = 0);
 
 // ---------------------------------------------------------------------------
 // stages

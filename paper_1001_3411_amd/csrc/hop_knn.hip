@@ -25,7 +25,8 @@
 //   3. stream: the listed leaves, in classes of increasing distance from
 //      the bucket's box, are loaded 64 particles at a time; each particle is
 //      tested by all lanes against their current bounds (exactly, in FP64)
-//      and the ones that pass are inserted lane by lane.  After the near
+//      and the ones that pass are inserted lane by lane, one batch behind
+//      (lanes done with a batch go on with the next one's).  After the near
 //      classes, and every 16 batches after that, the entries not streamed
 //      yet are tested again against the groups' tightened bounds and the
 //      list is compacted.
@@ -187,7 +188,10 @@ struct KnnArgs {
     double *dens_s;
     const int32_t *tk2j;
     uint32_t *dflags;
-    unsigned long long *counters;  // [0] nodes tested, [1] leaves scanned (NULL = off)
+    // (NULL = off) [0] nodes tested, [1] leaves scanned, [2] heap-insertion
+    // loop iterations, [3] candidates offered to a heap (those that pass
+    // the batch test against the lane's bound)
+    unsigned long long *counters;
     // learned radius (NULL = off): search radius per cell of side 2^cell_bits,
     // 2^cell_gb cells per axis; lanes whose list does not fit inside it are
     // recorded in miss[bucket] and write nothing
@@ -550,7 +554,19 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const double G = a.gsize;
     const int64_t n_leaf_total = a.lv.cnt[0];
-    unsigned long long n_nodes = 0, n_lv = 0;
+    // work counters (a.counters set: the same in every lane).  A loop that
+    // offers marked candidates one per lane per iteration runs exactly as
+    // many iterations as its busiest lane has offers, so both counts come
+    // from per-batch popcounts and nothing is added to the loops themselves
+    const bool counting = a.counters != nullptr;
+    unsigned long long n_nodes = 0, n_lv = 0, n_it = 0, n_off = 0;
+    auto count_offers = [&](uint64_t pass, uint32_t lane_iters) {
+        n_off += (unsigned long long)__popcll(pass);
+        uint32_t m = lane_iters;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d));
+        n_it += m;
+    };
 
     if (lane < bcount) stage[lane] = a.recs[b0 + lane];
     __syncthreads();
@@ -607,6 +623,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         return any ? key : ~0ull;
     };
     auto insert_marked = [&](uint64_t pass, bool wrap) {
+        if (counting) count_offers(pass, (uint32_t)__popcll(pass));
         bool have = pass != 0;
         uint64_t key = next_key(pass, wrap);
         if (!BIG && hs == kHeapMax) {
@@ -916,12 +933,44 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
         r = a.recs[idx];
         return true;
     };
+    // Offers are deferred by one batch: a batch's marked particles (po)
+    // wait in s_old while the next batch is staged and tested, and the
+    // insertion loop runs until the older batch is done, lanes that finish
+    // it early going on with the newer one (the loop runs as long as its
+    // busiest lane, so this evens out the lanes' work across batches).
+    // s_old alternates between the stage and heap slots 0..3, which are
+    // free while levels 0 and 1 are in registers.  The key read one ahead
+    // (dkey, dhave) is carried across batches.
+    SortedRec *s_cur = stage, *s_old = reinterpret_cast<SortedRec *>(heap);
+    uint64_t po = 0, dkey = ~0ull;
+    bool dhave = false;
+    auto next_key2 = [&](uint64_t &pn, bool wrap) -> uint64_t {
+        const bool from_old = po != 0;
+        const uint64_t p = from_old ? po : pn;
+        const bool any = p != 0;
+        const int k = __builtin_ctzll(p | (1ull << 63));
+        const uint64_t rest = p & (p - 1);
+        po = from_old ? rest : po;
+        pn = from_old ? pn : rest;
+        const SortedRec r = (from_old ? s_old : s_cur)[k];
+        const double d2 = wrap ? d2_wrap(qx, qy, qz, r, G) : d2_direct(qx, qy, qz, r);
+        const uint64_t key = make_key(d2, (uint32_t)r.tk, a);
+        return any ? key : ~0ull;
+    };
+    auto offer = [&]() {
+        if (!BIG && hs == kHeapMax) rh_replace_root63(H, heap, lane, (dhave && dkey < H.r0) ? dkey : H.r0);
+        else if (dhave && dkey < H.r0) rh_replace_root(H, heap, lane, hs, dkey);
+    };
     // one copy of the loop per distance form (FAST: images already chosen
     // by the loading lane, or no periodicity), so the tests carry no branch
     auto stream = [&](auto fast_tag) {
         constexpr bool FAST = decltype(fast_tag)::value;
         SortedRec nxt;
         bool nxt_ok = nbatch > 0 ? fetch(0, nxt) : false;
+        // wait for the first batch here (vmcnt(0)): left outstanding into the
+        // loop, it made the compiler wait for every batch's prefetch before
+        // that batch's tests, so the prefetch overlapped nothing
+        __builtin_amdgcn_s_waitcnt(0x0F70);
         int next_cut = bi_cut;
         for (int bi = 0; bi < nbatch; bi++) {
             if (bi == next_cut) {
@@ -955,7 +1004,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
                 r.tk = -1;
             }
             __syncthreads();
-            stage[lane] = r;
+            s_cur[lane] = r;
             if (FAST) stage_pp[lane] = __builtin_fma(r.x, r.x, __builtin_fma(r.y, r.y, r.z * r.z));
             __syncthreads();
             if (bi + 1 < nbatch) nxt_ok = fetch(bi + 1, nxt);
@@ -973,7 +1022,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
                 double pp[16];
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
-                    pr[k] = stage[k0 + k];
+                    pr[k] = s_cur[k0 + k];
                     if (FAST) pp[k] = stage_pp[k0 + k];
                 }
                 // (the bits go straight into the 64-bit mask: collecting them
@@ -992,11 +1041,39 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
                     pass |= (uint64_t)(ok_k ? 1u : 0u) << (k0 + k);
                 }
             }
-            insert_marked(pass, PERIODIC && !FAST);
+            // finish the older batch; lanes done with it take this one's
+            if (counting) count_offers(pass, (uint32_t)__popcll(po));
+            uint64_t pn = pass;
+            while (__any(po != 0)) {
+                const bool hn = (po | pn) != 0;
+                const uint64_t kn = next_key2(pn, PERIODIC && !FAST);
+                offer();
+                dhave = hn;
+                dkey = kn;
+            }
+            po = pn;
+            SortedRec *t = s_cur;
+            s_cur = s_old;
+            s_old = t;
+            if (active) tau = fmin(key_d2(H.r0, a.shift), rcap);
         }
     };
+    const bool wrap_tail = PERIODIC && !fastB;
     if (!PERIODIC || fastB) stream(std::true_type{});
     else stream(std::false_type{});
+    {
+        // the last batch's deferred offers
+        if (counting) count_offers(0, (uint32_t)__popcll(po) + ((dhave || po != 0) ? 1u : 0u));
+        uint64_t pn = 0;
+        while (__any(dhave || po != 0)) {
+            const bool hn = po != 0;
+            const uint64_t kn = next_key2(pn, wrap_tail);
+            offer();
+            dhave = hn;
+            dkey = kn;
+        }
+    }
+    __syncthreads();  // every read of s_old done before slots 0..4 are rewritten
     // write the register levels back so the heap is whole in LDS
     heap[lane] = H.r0;
 #pragma unroll
@@ -1005,6 +1082,13 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     if (a.counters && lane == 0) {
         atomicAdd(&a.counters[0], n_nodes);
         atomicAdd(&a.counters[1], n_lv);
+        atomicAdd(&a.counters[2], n_it);
+    }
+    if (counting) {
+        unsigned long long t = active ? n_off : 0ull;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) t += (unsigned long long)__shfl_xor((long long)t, d);
+        if (lane == 0) atomicAdd(&a.counters[3], t);
     }
     // a bounded search is exact for a lane whose whole list lies inside its
     // radius; the other lanes are searched again without it
@@ -1160,7 +1244,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
 template <bool PERIODIC, bool IDS, bool BIG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_density(KnnArgs a)
 {
-    __shared__ uint64_t heap[heap_slots<BIG>() * 64];
+    __shared__ __align__(16) uint64_t heap[heap_slots<BIG>() * 64];
     __shared__ uint32_t front[BIG ? 2 * kFrontLevelBig : 1];
     __shared__ SortedRec stage[64];
     __shared__ double stage_pp[64];
@@ -1179,7 +1263,7 @@ template <bool PERIODIC, bool IDS, bool BIG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_redo(
     KnnArgs a, const uint32_t *__restrict__ list, const unsigned long long *__restrict__ miss)
 {
-    __shared__ uint64_t heap[heap_slots<BIG>() * 64];
+    __shared__ __align__(16) uint64_t heap[heap_slots<BIG>() * 64];
     __shared__ uint32_t front[BIG ? 2 * kFrontLevelBig : 1];
     __shared__ SortedRec stage[64];
     __shared__ double stage_pp[64];
@@ -1212,7 +1296,7 @@ template <bool PERIODIC, bool BIG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_batch(KnnArgs a,
                                                                                              BatchArgs b)
 {
-    __shared__ uint64_t heap[heap_slots<BIG>() * 64];
+    __shared__ __align__(16) uint64_t heap[heap_slots<BIG>() * 64];
     __shared__ uint32_t front[BIG ? 2 * kFrontLevelBig : 1];
     __shared__ SortedRec stage[64];
     __shared__ double stage_pp[64];
@@ -1395,8 +1479,8 @@ int finish_stats(hop_ctx *ctx, Events &ev, const KnnArgs &a, int64_t n)
     } else {
         HOPCHK(ctx, hipEventElapsedTime(&t1, ev.e[1], ev.e[2]));
     }
-    unsigned long long c[2] = {0, 0};
-    if (a.counters) HOPCHK(ctx, hipMemcpy(c, a.counters, 16, hipMemcpyDeviceToHost));
+    unsigned long long c[4] = {0, 0, 0, 0};
+    if (a.counters) HOPCHK(ctx, hipMemcpy(c, a.counters, 32, hipMemcpyDeviceToHost));
     ctx->stats.ms_sort = t0;
     ctx->stats.ms_knn = t1;
     ctx->stats.ms_radius = tr;
@@ -1405,6 +1489,8 @@ int finish_stats(hop_ctx *ctx, Events &ev, const KnnArgs &a, int64_t n)
     ctx->stats.n = n;
     ctx->stats.nodes_visited = (int64_t)c[0];
     ctx->stats.leaves_scanned = (int64_t)c[1];
+    ctx->stats.insert_iterations = (int64_t)c[2];
+    ctx->stats.offered = (int64_t)c[3];
     return HOP_OK;
 }
 
@@ -1412,7 +1498,7 @@ int start_counters(hop_ctx *ctx, KnnArgs &a, hipStream_t s)
 {
     if (ctx->profiling & 2) {
         a.counters = (unsigned long long *)((char *)ctx->flags.ptr + 256);
-        HOPCHK(ctx, hipMemsetAsync(a.counters, 0, 16, s));
+        HOPCHK(ctx, hipMemsetAsync(a.counters, 0, 32, s));
     }
     return HOP_OK;
 }
@@ -1449,8 +1535,13 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     uint32_t *perm = (uint32_t *)ctx->vals_a.ptr;
     k_morton<<<hop_grid(n, 256), 256, 0, s>>>(pos, n, glim, keys, perm, dflags);
     HOPCHK(ctx, hipGetLastError());
+    // the top 48 bits of the code order cells of 2^(grid_bits - 16) grid
+    // units, far below the mean spacing at any n < 2^31: particles sharing
+    // a cell keep their input order, which only the locality of the search
+    // depends on (its result does not), and two radix passes are saved
+    const int code_bits = 3 * (int)p->grid_bits;
     HOPTRY(hop_radix_sort(ctx, keys, perm, (uint64_t *)ctx->keys_b.ptr, (uint32_t *)ctx->vals_b.ptr,
-                          n, 3 * (int)p->grid_bits, s));
+                          n, code_bits, s, std::max(0, code_bits - 48)));
     ctx->perm_n = n;
 
     // 2. sorted copy and tree

@@ -38,10 +38,13 @@ __device__ __forceinline__ uint64_t pair_hash(uint64_t k)
     return k;
 }
 
+// Per chain: its root and peak density, and the number of its members that
+// count towards a halo (padded particles do not under the padded rules).
 __global__ void k_chain_table(int64_t n, const int32_t *__restrict__ root,
                               const int32_t *__restrict__ chain_of, const double *__restrict__ dens,
-                              int32_t C, int32_t *__restrict__ croot, double *__restrict__ cpeak,
-                              uint32_t *__restrict__ dflags)
+                              const uint8_t *__restrict__ padded, int padded_rules, int32_t C,
+                              int32_t *__restrict__ croot, double *__restrict__ cpeak,
+                              uint32_t *__restrict__ ccount, uint32_t *__restrict__ dflags)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -55,10 +58,12 @@ __global__ void k_chain_table(int64_t n, const int32_t *__restrict__ root,
         atomicOr(dflags, DERR_INDEX);
         return;
     }
-    if (c >= 0 && r == (int32_t)i) {
+    if (c < 0) return;
+    if (r == (int32_t)i) {
         croot[c] = (int32_t)i;
         cpeak[c] = dens[i];
     }
+    if (!(padded_rules && padded && padded[i])) atomicAdd(&ccount[c], 1u);
 }
 
 __global__ void k_saddle_insert(int64_t n, const int32_t *__restrict__ nbr, int k_store,
@@ -270,18 +275,6 @@ __global__ void k_rooted(int32_t C, const int32_t *__restrict__ hp, const double
     if (cpeak[c] >= delta_peak) rooted[hp[c]] = 1u;
 }
 
-__global__ void k_chain_count(int64_t n, const int32_t *__restrict__ chain_of,
-                              const uint8_t *__restrict__ padded, int padded_rules, int32_t C,
-                              uint32_t *__restrict__ ccount)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t c = chain_of[i];
-    if (c < 0 || c >= C) return;
-    if (padded_rules && padded && padded[i]) return;
-    atomicAdd(&ccount[c], 1u);
-}
-
 __global__ void k_halo_accum(int32_t C, const int32_t *__restrict__ hp,
                              const uint32_t *__restrict__ rooted, const uint32_t *__restrict__ ccount,
                              const double *__restrict__ cpeak, uint32_t *__restrict__ hcount,
@@ -479,7 +472,9 @@ int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *de
     uint32_t *hcount = cv.take<uint32_t>(C1);
     int32_t *num = cv.take<int32_t>(C1);
 
-    k_chain_table<<<hop_grid(n, 256), 256, 0, s>>>(n, root, chain_of, density, C, croot, cpeak, dflags);
+    HOPCHK(ctx, hipMemsetAsync(ccount, 0, (size_t)C * 4, s));
+    k_chain_table<<<hop_grid(n, 256), 256, 0, s>>>(n, root, chain_of, density, padded, pr, C, croot,
+                                                   cpeak, ccount, dflags);
     HOPCHK(ctx, hipGetLastError());
 
     // --- boundary table -----------------------------------------------------
@@ -566,11 +561,9 @@ int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *de
     HOPCHK(ctx, hipGetLastError());
 
     // --- labels --------------------------------------------------------------
-    HOPCHK(ctx, hipMemsetAsync(ccount, 0, (size_t)C * 4, s));
     HOPCHK(ctx, hipMemsetAsync(hcount, 0, (size_t)C * 4, s));
     HOPCHK(ctx, hipMemsetAsync(hpeak, 0, (size_t)C * 8, s));
     HOPCHK(ctx, hipMemsetAsync(hptk, 0xff, (size_t)C * 4, s));
-    k_chain_count<<<hop_grid(n, 256), 256, 0, s>>>(n, chain_of, padded, pr, C, ccount);
     k_halo_accum<<<hop_grid(C, 256), 256, 0, s>>>(C, hp, rooted, ccount, cpeak, hcount, hpeak);
     k_halo_peak_tk<<<hop_grid(C, 256), 256, 0, s>>>(C, hp, rooted, cpeak, hpeak, croot, tk, hptk);
     HOPCHK(ctx, hipGetLastError());

@@ -223,9 +223,9 @@ int hop_scan_u32(hop_ctx *ctx, uint32_t *data, int64_t n, uint32_t *total_dev, h
 }
 
 int hop_radix_sort(hop_ctx *ctx, uint64_t *keys, uint32_t *vals, uint64_t *tkeys, uint32_t *tvals,
-                   int64_t n, int bits, hipStream_t s)
+                   int64_t n, int bits, hipStream_t s, int lo_bit)
 {
-    if (n <= 1 || bits <= 0) return HOP_OK;
+    if (n <= 1 || bits <= lo_bit) return HOP_OK;
     const int64_t nb = hop_div_up(n, kTile);
     if (nb * 256 >= (int64_t)1 << 31) return hop_fail(ctx, HOP_ERR_ARG, "radix sort too large");
     DevBuf &hb = ctx->work_f;
@@ -234,7 +234,7 @@ int hop_radix_sort(hop_ctx *ctx, uint64_t *keys, uint32_t *vals, uint64_t *tkeys
     uint64_t *ka = keys, *kb = tkeys;
     uint32_t *va = vals, *vb = tvals;
     int passes = 0;
-    for (int shift = 0; shift < bits; shift += 8, passes++) {
+    for (int shift = lo_bit; shift < bits; shift += 8, passes++) {
         k_radix_hist<<<(int)nb, kThreads, 0, s>>>(ka, n, shift, nb, hist);
         HOPCHK(ctx, hipGetLastError());
         HOPTRY(hop_scan_u32(ctx, hist, nb * 256, nullptr, s));

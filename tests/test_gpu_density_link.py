@@ -128,3 +128,34 @@ def test_abi_rejects_null_nbr_for_long_links(ctx):
     with pytest.raises(HopError):
         ctx.density_link(p.pos, HopParams(mean_density=p.mean_density, n_dens=32, n_hop=24,
                                           n_merge=4, k_store=32), want_nbr=False)
+
+
+def test_work_counters(ctx):
+    """Profiling bit 2 counts the kNN kernel's work on the device: tree
+    nodes tested, leaves streamed, heap-insertion loop iterations (each for
+    the whole wave) and candidates offered to a lane's heap (each costs that
+    lane one iteration, so a bucket's lanes together are offered at most 64
+    per iteration).  Counting leaves the outputs unchanged; one bucket of 64
+    particles with N_dens = 64 fills every heap with its 63 others
+    directly, so nothing is offered."""
+    from paper_1001_3411_amd import HopParams
+    p = synth.config(1)
+    prm = HopParams(mean_density=p.mean_density)
+    ctx.set_profiling(0)
+    d0, n0 = ctx.density(p.pos, prm)
+    ctx.set_profiling(3)
+    d1, n1 = ctx.density(p.pos, prm)
+    st = ctx.stats()
+    ctx.set_profiling(0)
+    assert np.array_equal(_np(d0), _np(d1)) and np.array_equal(_np(n0), _np(n1))
+    it, off = st["insert_iterations"], st["offered"]
+    print(f"[counters] {p.name}: {it / ((p.n + 63) // 64):.1f} insertion iterations per bucket, "
+          f"{off / p.n:.1f} offered per query, {st['nodes_visited'] / p.n:.1f} nodes per query",
+          flush=True)
+    assert 0 < off <= 64 * it and st["nodes_visited"] > 0 and st["leaves_scanned"] > 0
+    q = synth.tiny_case("uniform", 64, 3)
+    ctx.set_profiling(3)
+    ctx.density(q.pos, HopParams(mean_density=q.mean_density, periodic=q.periodic))
+    st = ctx.stats()
+    ctx.set_profiling(0)
+    assert st["insert_iterations"] == 0 and st["offered"] == 0

@@ -133,3 +133,58 @@ def test_bounded_search_is_exact(ctx, orc, box1):
     st = _exact_with(ctx, orc, p, prm, "all-miss")
     assert st["misses"] == p.n
     ctx.radius_load(0)
+
+
+def test_search_modes_on_the_clustered_box(ctx):
+    """The 16.8M-particle Zel'dovich box under the plain search, the analytic
+    radius and the trained network (each calibrated for a 1% miss rate):
+    neighbour lists, densities, links and groups are the same in all three,
+    and the work each does (tree nodes tested, leaf batches streamed,
+    misses searched again, kNN time) is recorded."""
+    import time
+    from dataclasses import replace
+
+    import torch
+    from paper_1001_3411_amd import HOP_RADIUS_ANALYTIC, HOP_RADIUS_MLP, HopParams
+    from paper_1001_3411_amd.radius import calibrate, cell_bits_for, train
+    p = synth.config(3)
+    prm = HopParams(mean_density=p.mean_density)
+    pos = torch.from_numpy(p.pos.view(np.int32)).cuda()
+    _, nbr = ctx.density(pos, prm)
+    feats, target = ctx.radius_dataset(pos, prm, cell_bits_for(p.n), nbr=nbr)
+    del nbr
+    w, losses = train(ctx, feats, target, steps=1500, batch=4096, seed=0)
+    models = {"analytic": (HOP_RADIUS_ANALYTIC, None), "mlp": (HOP_RADIUS_MLP, w)}
+    margins = {k: calibrate(ctx, m[1], feats, target, miss_rate=0.01, kind=m[0])
+               for k, m in models.items()}
+    del feats, target
+    ref, rows = None, {}
+    for name in ("plain", "analytic", "mlp"):
+        q = prm
+        if name != "plain":
+            ctx.radius_load(models[name][0], models[name][1], margins[name])
+            q = replace(prm, learned_radius=True)
+        ctx.set_profiling(3)
+        out = ctx.run(pos, q)
+        st = ctx.stats()
+        ctx.set_profiling(1)
+        ms = []
+        for _ in range(3):
+            ctx.run(pos, q)
+            ms.append(ctx.stats()["ms_knn"])
+        ctx.set_profiling(0)
+        got = {k: out[k] for k in ("nbr", "density", "hop", "group")}
+        if ref is None:
+            ref = got
+        else:
+            for k in ref:
+                assert torch.equal(got[k], ref[k]), (name, k)
+        rows[name] = (st["nodes_visited"] / p.n, st["leaves_scanned"] / p.n / 4,
+                      st["misses"] / p.n, float(np.median(ms)))
+        print(f"[radius] {p.name} {name}: nodes/particle {rows[name][0]:.2f}, leaf batches/"
+              f"particle {rows[name][1]:.3f}, miss fraction {rows[name][2]:.4f}, "
+              f"kNN {rows[name][3]:.1f} ms", flush=True)
+        del out, got
+    ctx.radius_load(0)
+    assert rows["plain"][2] == 0.0
+    assert 0.0 < rows["mlp"][2] < 0.05 and 0.0 < rows["analytic"][2] < 0.05
