@@ -542,7 +542,11 @@ typedef struct hop_stats {
                                two chains inside a subvolume; hop_subhalos:
                                symmetric chain boundaries                        */
     int64_t insert_iterations; /* kNN: heap-insertion loop iterations, summed
-                                  over buckets (each runs for all 64 lanes)     */
+                                  over buckets (each runs for all 64 lanes);
+                                  this and `offered` are counted by the main
+                                  search of hop_density / hop_density_link, not
+                                  by a learned-radius fallback pass or by
+                                  hop_run_batch                                */
     int64_t offered;        /* kNN: candidates offered to a lane's heap (those
                                within the lane's bound when their batch was
                                tested; each costs the lane one iteration)        */

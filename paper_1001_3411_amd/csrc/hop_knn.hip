@@ -57,6 +57,18 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v)
     return x;
 }
 
+// inverse of spread3: every third bit of v, from bit 0
+__device__ __forceinline__ uint32_t compact3(uint64_t v)
+{
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return (uint32_t)v;
+}
+
 __global__ void k_morton(const uint32_t *__restrict__ pos, int64_t n, uint32_t glim,
                          uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                          uint32_t *__restrict__ dflags)
@@ -74,17 +86,26 @@ __global__ void k_morton(const uint32_t *__restrict__ pos, int64_t n, uint32_t g
     vals[i] = (uint32_t)i;
 }
 
-__global__ void k_gather_recs(const uint32_t *__restrict__ pos, const uint32_t *__restrict__ perm,
-                              const int32_t *__restrict__ tk, int64_t n, uint32_t glim,
-                              SortedRec *__restrict__ recs)
+// codes: the sorted full Morton codes, which hold the (clamped) coordinates
+// themselves, so that no position is gathered; NULL: gather from pos.
+__global__ void k_gather_recs(const uint32_t *__restrict__ pos, const uint64_t *__restrict__ codes,
+                              const uint32_t *__restrict__ perm, const int32_t *__restrict__ tk,
+                              int64_t n, uint32_t glim, SortedRec *__restrict__ recs)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     int32_t j = (int32_t)perm[t];
     SortedRec r;
-    r.x = (double)min(pos[3 * (int64_t)j], glim - 1);
-    r.y = (double)min(pos[3 * (int64_t)j + 1], glim - 1);
-    r.z = (double)min(pos[3 * (int64_t)j + 2], glim - 1);
+    if (codes) {
+        const uint64_t c = codes[t];
+        r.x = (double)compact3(c >> 2);
+        r.y = (double)compact3(c >> 1);
+        r.z = (double)compact3(c);
+    } else {
+        r.x = (double)min(pos[3 * (int64_t)j], glim - 1);
+        r.y = (double)min(pos[3 * (int64_t)j + 1], glim - 1);
+        r.z = (double)min(pos[3 * (int64_t)j + 2], glim - 1);
+    }
     r.j = j;
     r.tk = tk ? tk[j] : j;
     recs[t] = r;
@@ -535,7 +556,7 @@ __device__ __forceinline__ void rh_replace_root(RegHeap &H, uint64_t *heap, int 
 // levels in LDS, and the walk's frontier in LDS of its own, `front`);
 // otherwise n_dens up to 64 and the frontier borrows the heap's LDS while
 // the heap's deeper levels are parked in registers (front is unused).
-template <bool PERIODIC, bool IDS, bool BIG>
+template <bool PERIODIC, bool IDS, bool BIG, bool COUNT>
 __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, const int bcount,
                                            const int64_t plo, const int64_t phi,
                                            const double norm, const float norm32, uint64_t *heap,
@@ -554,11 +575,13 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const double G = a.gsize;
     const int64_t n_leaf_total = a.lv.cnt[0];
-    // work counters (a.counters set: the same in every lane).  A loop that
+    // work counters (COUNT instances with a.counters set).  A loop that
     // offers marked candidates one per lane per iteration runs exactly as
     // many iterations as its busiest lane has offers, so both counts come
-    // from per-batch popcounts and nothing is added to the loops themselves
-    const bool counting = a.counters != nullptr;
+    // from per-batch popcounts and nothing is added to the loops themselves;
+    // they live in instances of their own, because their mere presence
+    // slowed the kernel by 1.4% with counting off
+    const bool counting = COUNT && a.counters != nullptr;
     unsigned long long n_nodes = 0, n_lv = 0, n_it = 0, n_off = 0;
     auto count_offers = [&](uint64_t pass, uint32_t lane_iters) {
         n_off += (unsigned long long)__popcll(pass);
@@ -1241,7 +1264,7 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
 // One box: one wave per bucket of 64 sorted particles.  Consecutive blocks
 // land on different XCDs, so each XCD gets a contiguous run of buckets
 // (neighbouring buckets share candidate leaves in that XCD's L2).
-template <bool PERIODIC, bool IDS, bool BIG>
+template <bool PERIODIC, bool IDS, bool BIG, bool COUNT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_knn_density(KnnArgs a)
 {
     __shared__ __align__(16) uint64_t heap[heap_slots<BIG>() * 64];
@@ -1253,8 +1276,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     const int64_t bucket = (bid & 7) * a.xcd_chunk + (bid >> 3);
     if (bucket >= a.n_buckets) return;
     const int64_t b0 = bucket * HOP_BUCKET;
-    knn_bucket<PERIODIC, IDS, BIG>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n, a.norm,
-                                   a.norm32, heap, front, stage, stage_pp, leaves, ~0ull, bucket);
+    knn_bucket<PERIODIC, IDS, BIG, COUNT>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n,
+                                          a.norm, a.norm32, heap, front, stage, stage_pp, leaves,
+                                          ~0ull, bucket);
 }
 
 // Fallback of a bounded search: the listed buckets again, without a radius,
@@ -1270,9 +1294,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     __shared__ uint32_t leaves[kLeafList];
     const int64_t bucket = list[blockIdx.x];
     const int64_t b0 = bucket * HOP_BUCKET;
-    knn_bucket<PERIODIC, IDS, BIG>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n, a.norm,
-                                   a.norm32, heap, front, stage, stage_pp, leaves, miss[bucket],
-                                   bucket);
+    knn_bucket<PERIODIC, IDS, BIG, false>(a, b0, (int)min((int64_t)HOP_BUCKET, a.n - b0), 0, a.n,
+                                          a.norm, a.norm32, heap, front, stage, stage_pp, leaves,
+                                          miss[bucket], bucket);
 }
 
 // buckets with a recorded miss -> list; count the missed lanes
@@ -1327,7 +1351,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         const int64_t plo = b.sub_off[sv], phi = b.sub_off[sv + 1];
         const int64_t b0 = plo + (item - b.item_off[lo]) * HOP_BUCKET;
         __syncthreads();
-        knn_bucket<PERIODIC, false, BIG>(a, b0, (int)min((int64_t)HOP_BUCKET, phi - b0), plo, phi,
+        knn_bucket<PERIODIC, false, BIG, false>(a, b0, (int)min((int64_t)HOP_BUCKET, phi - b0), plo, phi,
                                          b.norm[sv], b.norm32[sv], heap, front, stage, stage_pp,
                                          leaves, ~0ull, 0);
         if (lane == 0) atomicAdd(&b.done[sv], 1u);
@@ -1389,13 +1413,13 @@ struct Events {
 };
 
 // Sorted copy (permutation in ctx->vals_a) and the implicit tree over it.
-int build_tree(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int32_t *tk, uint32_t glim,
-               hipStream_t s, TreeLevels &lv, SortedRec *&recs, NodeBox *&boxes)
+int build_tree(hop_ctx *ctx, int64_t n, const uint32_t *pos, const uint64_t *codes, const int32_t *tk,
+               uint32_t glim, hipStream_t s, TreeLevels &lv, SortedRec *&recs, NodeBox *&boxes)
 {
     const uint32_t *perm = (const uint32_t *)ctx->vals_a.ptr;
     HOPTRY(hop_reserve(ctx, ctx->recs, (size_t)n * sizeof(SortedRec)));
     recs = (SortedRec *)ctx->recs.ptr;
-    k_gather_recs<<<hop_grid(n, 256), 256, 0, s>>>(pos, perm, tk, n, glim, recs);
+    k_gather_recs<<<hop_grid(n, 256), 256, 0, s>>>(pos, codes, perm, tk, n, glim, recs);
     HOPCHK(ctx, hipGetLastError());
 
     lv = TreeLevels{};
@@ -1494,6 +1518,14 @@ int finish_stats(hop_ctx *ctx, Events &ev, const KnnArgs &a, int64_t n)
     return HOP_OK;
 }
 
+// the counting instance only when counters are on
+template <bool PERIODIC, bool IDS, bool BIG>
+void launch_density(const KnnArgs &a, int64_t grid, hipStream_t s)
+{
+    if (a.counters) k_knn_density<PERIODIC, IDS, BIG, true><<<(int)grid, 64, 0, s>>>(a);
+    else k_knn_density<PERIODIC, IDS, BIG, false><<<(int)grid, 64, 0, s>>>(a);
+}
+
 int start_counters(hop_ctx *ctx, KnnArgs &a, hipStream_t s)
 {
     if (ctx->profiling & 2) {
@@ -1548,7 +1580,7 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     TreeLevels lv;
     SortedRec *recs = nullptr;
     NodeBox *boxes = nullptr;
-    HOPTRY(build_tree(ctx, n, pos, tk, glim, s, lv, recs, boxes));
+    HOPTRY(build_tree(ctx, n, pos, keys, tk, glim, s, lv, recs, boxes));
     if (ctx->profiling) HOPCHK(ctx, hipEventRecord(ev.e[1], s));
 
     // 3. kNN + density (bounded by the per-cell search radius if asked for)
@@ -1572,18 +1604,18 @@ int hop_density_impl(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     const bool big = p->n_dens > kHeapMax + 1;
     if (big) {
         if (periodic) {
-            if (id) k_knn_density<true, true, true><<<(int)grid, 64, 0, s>>>(a);
-            else k_knn_density<true, false, true><<<(int)grid, 64, 0, s>>>(a);
+            if (id) launch_density<true, true, true>(a, grid, s);
+            else launch_density<true, false, true>(a, grid, s);
         } else {
-            if (id) k_knn_density<false, true, true><<<(int)grid, 64, 0, s>>>(a);
-            else k_knn_density<false, false, true><<<(int)grid, 64, 0, s>>>(a);
+            if (id) launch_density<false, true, true>(a, grid, s);
+            else launch_density<false, false, true>(a, grid, s);
         }
     } else if (periodic) {
-        if (id) k_knn_density<true, true, false><<<(int)grid, 64, 0, s>>>(a);
-        else k_knn_density<true, false, false><<<(int)grid, 64, 0, s>>>(a);
+        if (id) launch_density<true, true, false>(a, grid, s);
+        else launch_density<true, false, false>(a, grid, s);
     } else {
-        if (id) k_knn_density<false, true, false><<<(int)grid, 64, 0, s>>>(a);
-        else k_knn_density<false, false, false><<<(int)grid, 64, 0, s>>>(a);
+        if (id) launch_density<false, true, false>(a, grid, s);
+        else launch_density<false, false, false>(a, grid, s);
     }
     HOPCHK(ctx, hipGetLastError());
     int64_t misses = 0, redo = 0;
@@ -1696,7 +1728,8 @@ int hop_density_batch_impl(hop_ctx *ctx, int32_t n_sub, const int64_t *off, cons
     TreeLevels lv;
     SortedRec *recs = nullptr;
     NodeBox *boxes = nullptr;
-    HOPTRY(build_tree(ctx, n, pos, nullptr, glim, s, lv, recs, boxes));
+    // (the batch keys drop low code bits: positions are gathered)
+    HOPTRY(build_tree(ctx, n, pos, nullptr, nullptr, glim, s, lv, recs, boxes));
     if (ctx->profiling) HOPCHK(ctx, hipEventRecord(ev.e[1], s));
 
     // 3. persistent kNN + density over all buckets of all subvolumes
