@@ -111,19 +111,55 @@ __global__ void k_saddle_insert(int64_t n, const int32_t *__restrict__ nbr, int 
     }
 }
 
+// Compaction of the boundary hash (the order of the compacted edges is
+// immaterial: the merge orders edges by saddle density and key itself).
+// Atomics on one counter serialise in the L2, so each wave takes a run of
+// kCompactRounds * 64 consecutive slots: it counts its kept slots, takes
+// its output range with one atomic, then writes them.
+constexpr int kCompactRounds = 64;
+
+template <typename Keep, typename Emit>
+__device__ __forceinline__ void wave_compact(int64_t cap, uint32_t *count, Keep keep, Emit emit)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t first = wave * 64 * kCompactRounds;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    uint32_t total = 0;
+    for (int r = 0; r < kCompactRounds; r++) {
+        const int64_t t = first + (int64_t)r * 64 + lane;
+        total += (uint32_t)__popcll(__ballot(t < cap && keep(t)));
+    }
+    uint32_t base = 0;
+    if (lane == 0 && total != 0) base = atomicAdd(count, total);
+    base = (uint32_t)__shfl((int)base, 0);
+    for (int r = 0; r < kCompactRounds; r++) {
+        const int64_t t = first + (int64_t)r * 64 + lane;
+        const bool k = t < cap && keep(t);
+        const uint64_t m = __ballot(k);
+        if (k) emit(t, base + (uint32_t)__popcll(m & lt));
+        base += (uint32_t)__popcll(m);
+    }
+}
+
+static inline int compact_grid(int64_t cap)
+{
+    return hop_grid(hop_div_up(cap, kCompactRounds), 256);
+}
+
 __global__ void k_edge_compact(int64_t cap, const uint64_t *__restrict__ hkeys,
                                const unsigned long long *__restrict__ hvals,
                                int32_t *__restrict__ elo, int32_t *__restrict__ ehi,
                                uint64_t *__restrict__ es, uint32_t *__restrict__ count)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= cap) return;
-    uint64_t k = hkeys[t];
-    if (k == kEmpty) return;
-    uint32_t at = atomicAdd(count, 1u);
-    elo[at] = (int32_t)(k >> 32);
-    ehi[at] = (int32_t)(k & 0xffffffffu);
-    es[at] = hvals[t];
+    wave_compact(
+        cap, count, [&](int64_t t) { return hkeys[t] != kEmpty; },
+        [&](int64_t t, uint32_t at) {
+            const uint64_t k = hkeys[t];
+            elo[at] = (int32_t)(k >> 32);
+            ehi[at] = (int32_t)(k & 0xffffffffu);
+            es[at] = hvals[t];
+        });
 }
 
 __global__ void k_bor_init(int32_t C, const double *__restrict__ cpeak, double delta_peak,
@@ -511,7 +547,7 @@ int hop_merge_impl(hop_ctx *ctx, int64_t n, const int32_t *nbr, const double *de
         HOPTRY(hop_reserve(ctx, ctx->edges_lo, (size_t)cap * 4));
         HOPTRY(hop_reserve(ctx, ctx->edges_hi, (size_t)cap * 4));
         HOPTRY(hop_reserve(ctx, ctx->edges_s, (size_t)cap * 8));
-        k_edge_compact<<<hop_grid(cap, 256), 256, 0, s>>>(
+        k_edge_compact<<<compact_grid(cap), 256, 0, s>>>(
             cap, hk, hv, (int32_t *)ctx->edges_lo.ptr, (int32_t *)ctx->edges_hi.ptr,
             (uint64_t *)ctx->edges_s.ptr, dcnt);
         HOPCHK(ctx, hipGetLastError());
@@ -670,14 +706,15 @@ __global__ void k_sym_compact(int64_t cap, const uint64_t *__restrict__ hkeys,
                               int32_t *__restrict__ elo, int32_t *__restrict__ ehi,
                               double *__restrict__ es, uint32_t *__restrict__ count)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= cap) return;
-    const uint64_t k = hkeys[t];
-    if (k == kEmpty || hup[t] == 0ull || hdown[t] == 0ull) return;
-    const uint32_t at = atomicAdd(count, 1u);
-    elo[at] = (int32_t)(k >> 32);
-    ehi[at] = (int32_t)(k & 0xffffffffu);
-    es[at] = __longlong_as_double((long long)min(hup[t], hdown[t]));
+    wave_compact(
+        cap, count,
+        [&](int64_t t) { return hkeys[t] != kEmpty && hup[t] != 0ull && hdown[t] != 0ull; },
+        [&](int64_t t, uint32_t at) {
+            const uint64_t k = hkeys[t];
+            elo[at] = (int32_t)(k >> 32);
+            ehi[at] = (int32_t)(k & 0xffffffffu);
+            es[at] = __longlong_as_double((long long)min(hup[t], hdown[t]));
+        });
 }
 
 __global__ void k_union_level(int64_t E, const int32_t *__restrict__ elo,
@@ -851,7 +888,7 @@ extern "C" int hop_subhalos(hop_ctx *ctx, int64_t n, const int32_t *nbr, const d
         const uint64_t *hk = (const uint64_t *)ctx->hash_keys.ptr;
         const unsigned long long *hup = (const unsigned long long *)ctx->hash_vals.ptr;
         HOPCHK(ctx, hipMemsetAsync(dcnt, 0, 4, s));
-        k_sym_compact<<<hop_grid(cap, 256), 256, 0, s>>>(cap, hk, hup, hup + cap, elo, ehi, es, dcnt);
+        k_sym_compact<<<compact_grid(cap), 256, 0, s>>>(cap, hk, hup, hup + cap, elo, ehi, es, dcnt);
         HOPCHK(ctx, hipGetLastError());
         HOPCHK(ctx, hipMemcpyAsync(ctx->hflags + 2, dcnt, 4, hipMemcpyDeviceToHost, s));
         HOPCHK(ctx, hipStreamSynchronize(s));

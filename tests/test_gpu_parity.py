@@ -215,3 +215,22 @@ def test_coarse_leaf_ranges_parity(orc):
             assert_parity(g, r, f"coarse-{p.name}")
     finally:
         c.close()
+
+
+def test_dense_cells_parity(ctx, orc):
+    """The Morton sort orders particles by the top 48 code bits only (cells
+    of 32 grid units); particles sharing such a cell keep their input
+    order.  Half of this box lies in a 48^3 cube, so many share cells, in
+    shuffled input order, with coincident positions among them: every
+    output still equals the oracle's."""
+    rng = np.random.default_rng(77)
+    blob = rng.integers(1_000_000, 1_000_048, size=(3000, 3), dtype=np.uint32)
+    blob[:40] = blob[40:80]  # some coincident pairs
+    back = rng.integers(0, 1 << 21, size=(3000, 3), dtype=np.uint32)
+    pos = np.concatenate([blob, back])[rng.permutation(6000)]
+    p = synth.Particles(pos=pos, periodic=True, mean_density=6000 / float(1 << 21) ** 3,
+                        name="dense_cells")
+    r = orc.run(p.pos, mean_density=p.mean_density)
+    g = gpu_run(ctx, p, _params(p))
+    assert r.n_groups >= 1
+    assert_parity(g, r, "dense-cells")
