@@ -1036,31 +1036,45 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
             // the query itself never appears here: its own bucket lies in the
             // seeded range, which the loader skips
             uint64_t pass = 0;
-            // FAST: d^2 <= tau  <=>  |p|^2 - 2 p.q <= tau - |q|^2, every term
-            // an integer below 2^53, so the three FMAs below are exact
-            const double tq = tau < 0.0 ? -1.0e300 : tau - qq;
+            if (FAST) {
+                // s = |p|^2 - 2 p.q - (tau - |q|^2) - 1/2 = d^2 - tau - 1/2:
+                // every partial sum a multiple of 1/2 below 2^52, so the FMAs
+                // are exact, and d^2 <= tau exactly when s < 0.  The sign bit
+                // of s's high word is shifted into the mask (v_alignbit),
+                // candidate k ending at bit k.  (tau < 0: no candidate.)
+                const double tq = tau < 0.0 ? -1.0e300 : tau - qq;
+                const double ntq = -(tq + 0.5);
+                uint32_t wlo = 0u, whi = 0u;
 #pragma unroll
-            for (int k0 = 0; k0 < 64; k0 += 16) {
-                SortedRec pr[16];
-                double pp[16];
+                for (int k0 = 48; k0 >= 0; k0 -= 16) {
+                    SortedRec pr[16];
+                    double pp[16];
 #pragma unroll
-                for (int k = 0; k < 16; k++) {
-                    pr[k] = s_cur[k0 + k];
-                    if (FAST) pp[k] = stage_pp[k0 + k];
-                }
-                // (the bits go straight into the 64-bit mask: collecting them
-                // in a 16-bit word first gave wrong lists in the persistent
-                // batch kernel with this toolchain)
-#pragma unroll
-                for (int k = 0; k < 16; k++) {
-                    bool ok_k;
-                    if (FAST) {
-                        const double e = __builtin_fma(m2x, pr[k].x, __builtin_fma(m2y, pr[k].y,
-                                                       __builtin_fma(m2z, pr[k].z, pp[k])));
-                        ok_k = e <= tq;
-                    } else {
-                        ok_k = d2_wrap(qx, qy, qz, pr[k], G) <= tau;
+                    for (int k = 0; k < 16; k++) {
+                        pr[k] = s_cur[k0 + k];
+                        pp[k] = stage_pp[k0 + k];
                     }
+#pragma unroll
+                    for (int k = 15; k >= 0; k--) {
+                        const double sv = __builtin_fma(m2x, pr[k].x, __builtin_fma(m2y, pr[k].y,
+                                                        __builtin_fma(m2z, pr[k].z, pp[k] + ntq)));
+                        const uint32_t sh = (uint32_t)((uint64_t)__double_as_longlong(sv) >> 32);
+                        if (k0 + k >= 32) whi = __builtin_amdgcn_alignbit(whi, sh, 31);
+                        else wlo = __builtin_amdgcn_alignbit(wlo, sh, 31);
+                    }
+                }
+                pass = ((uint64_t)whi << 32) | wlo;
+            }
+#pragma unroll
+            for (int k0 = 0; k0 < 64 && !FAST; k0 += 16) {
+                SortedRec pr[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) pr[k] = s_cur[k0 + k];
+                // per-pair minimum image (the bits go straight into the 64-bit
+                // mask, shifted as 64-bit values)
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    const bool ok_k = d2_wrap(qx, qy, qz, pr[k], G) <= tau;
                     pass |= (uint64_t)(ok_k ? 1u : 0u) << (k0 + k);
                 }
             }
