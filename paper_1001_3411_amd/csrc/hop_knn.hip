@@ -673,13 +673,14 @@ __device__ __forceinline__ void knn_bucket(const KnnArgs &a, const int64_t b0, c
     //    Nearest buckets first; the two buckets at distance d go in two
     //    batches that each take one half of both (lanes 0-31 from bucket -d,
     //    lanes 32-63 from bucket +d), so the lanes near either side share
-    //    each batch's insertions
+    //    each batch's insertions; the halves next to the bucket go first
     for (int si = 0; si < 2 * kSeedSides + 1; si++) {
         if (si == 0 && hs >= HOP_BUCKET - 1) continue;
         int64_t idx = b0 + lane;
         if (si > 0) {
             const int64_t d = (si + 1) >> 1;
-            idx = (lane < 32 ? b0 - d * HOP_BUCKET : b0 + d * HOP_BUCKET) + 32 * ((si - 1) & 1) + (lane & 31);
+            const int near_first = lane < 32 ? (si & 1) : ((si - 1) & 1);
+            idx = (lane < 32 ? b0 - d * HOP_BUCKET : b0 + d * HOP_BUCKET) + 32 * near_first + (lane & 31);
         }
         const bool here = si == 0 ? lane < bcount : (idx >= plo && idx < phi);
         const uint64_t vm = __ballot(here);
