@@ -27,7 +27,7 @@
 //      tested by all lanes against their current bounds (exactly, in FP64)
 //      and the ones that pass are inserted lane by lane, one batch behind
 //      (lanes done with a batch go on with the next one's).  After the near
-//      classes, and every 16 batches after that, the entries not streamed
+//      classes, and every 24 batches after that, the entries not streamed
 //      yet are tested again against the groups' tightened bounds and the
 //      list is compacted.
 // Only pruning depends on the bounds; every particle that could belong to
@@ -166,11 +166,11 @@ constexpr int kSeedSides = HOP_SEED_SIDES;  // Morton-neighbour buckets seeded o
 #endif
 constexpr int kListClasses = HOP_LIST_CLASSES;  // distance classes of the leaf list
 #ifndef HOP_NEAR_CLASSES
-#define HOP_NEAR_CLASSES 4
+#define HOP_NEAR_CLASSES 5
 #endif
 constexpr int kNearClasses = HOP_NEAR_CLASSES;  // classes streamed before the list is pruned again
 #ifndef HOP_PRUNE_EVERY
-#define HOP_PRUNE_EVERY 16
+#define HOP_PRUNE_EVERY 24
 #endif
 constexpr int kPruneEvery = HOP_PRUNE_EVERY;  // batches between later prunings
 constexpr int kWindow = 32;                    // stream positions per interleave window
