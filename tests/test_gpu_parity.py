@@ -234,3 +234,24 @@ def test_dense_cells_parity(ctx, orc):
     g = gpu_run(ctx, p, _params(p))
     assert r.n_groups >= 1
     assert_parity(g, r, "dense-cells")
+
+
+@pytest.mark.parametrize("gb", [12, 16])
+def test_smaller_grids_parity(ctx, orc, gb):
+    """Periodic boxes of side 2^12 and 2^16: the Morton codes have 36 and 48
+    bits (all of them sorted) and the sorted coordinates are decoded from
+    them; a clustered set with coincident points, every output equal to the
+    oracle's."""
+    rng = np.random.default_rng(100 + gb)
+    side = 1 << gb
+    n = 5000
+    centre = rng.integers(0, side, size=3)
+    blob = (centre + rng.normal(0, side / 200, size=(n // 2, 3))).astype(np.int64) % side
+    back = rng.integers(0, side, size=(n - n // 2, 3))
+    pos = np.concatenate([blob, back]).astype(np.uint32)[rng.permutation(n)]
+    prm = orc.HopParams(grid_bits=gb, delta_outer=10.0, delta_saddle=25.0, delta_peak=30.0)
+    r = orc.run(pos, mean_density=n / float(side) ** 3, params=prm)
+    p = synth.Particles(pos=pos, periodic=True, mean_density=n / float(side) ** 3, name=f"grid{gb}")
+    g = gpu_run(ctx, p, _params(p, grid_bits=gb, delta_outer=10.0, delta_saddle=25.0, delta_peak=30.0))
+    assert r.n_groups >= 1
+    assert_parity(g, r, f"grid-{gb}")
