@@ -433,8 +433,9 @@ int hop_run_batch(hop_ctx *ctx, int32_t n_sub, const int64_t *offsets, const uin
  * front_cap         frontier entries the kNN walk may produce before it
  *                   stops descending and streams whole subtrees (1..1024,
  *                   default 1024)
- * persistent_waves  waves of the batched kNN launch (0 = 4 per compute unit,
- *                   one per SIMD, the most that fit)
+ * persistent_waves  waves of the persistent kNN launches, of one box and of
+ *                   a batch (0 = as many as fit: 4 per compute unit, one
+ *                   per SIMD, or 2 when n_dens > 64; at least 8)
  * xcd_queues        batched launch: 1 = one work chunk per XCD, idle waves
  *                   move on to the other chunks (default); 0 = one queue
  * largest_first     batched launch: 1 = subvolumes in decreasing size

@@ -217,6 +217,32 @@ def test_coarse_leaf_ranges_parity(orc):
         c.close()
 
 
+@pytest.mark.parametrize("waves", [8, 37, 5000])
+def test_persistent_waves_parity(orc, waves):
+    """The one-box kNN kernel is a persistent launch whose workgroups take
+    buckets from 8 per-XCD queues and move on to the other queues when
+    theirs is empty: with the fewest waves allowed, a count that divides
+    nothing evenly, and more waves than buckets (capped), every output
+    equals the oracle's, for the 63-key heap and the 127-key heap."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1001_3411_amd import HopContext
+    c = HopContext(0)
+    c.set_tuning(persistent_waves=waves)
+    try:
+        p = synth.config(1)
+        r = orc.run(p.pos, periodic=p.periodic, mean_density=p.mean_density)
+        assert_parity(gpu_run(c, p, _params(p)), r, f"waves{waves}-{p.name}")
+        q = synth.tiny_case("clustered", 4097, 31)
+        prm = orc.HopParams(n_dens=128, n_hop=32, n_merge=8, k_store=100)
+        r = orc.run(q.pos, mean_density=q.mean_density, params=prm)
+        g = gpu_run(c, q, _params(q, n_dens=128, n_hop=32, n_merge=8, k_store=100))
+        assert_parity(g, r, f"waves{waves}-ndens128")
+    finally:
+        c.close()
+
+
 def test_dense_cells_parity(ctx, orc):
     """The Morton sort orders particles by the top 48 code bits only (cells
     of 32 grid units); particles sharing such a cell keep their input
