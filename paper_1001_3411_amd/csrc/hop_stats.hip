@@ -31,15 +31,38 @@ __device__ __forceinline__ int64_t min_image(int64_t d, int periodic, int64_t G)
 // block and sum, so the largest halos do not serialise on a few addresses.
 // The blocks stride over the particles (a fixed grid), so each block's
 // flush is paid once for many particles.
+//
+// The particles are taken in the order of `order` when it is given (the
+// sorted copy of the last kNN call on n particles: Morton order, a
+// permutation of [0, n)), else in input order.  In Morton order the 64
+// lanes of a wave are neighbours in space and mostly members of one halo,
+// so each wave first adds up its runs of lanes with equal halo numbers
+// (a segmented scan over the lanes) and the last lane of each run makes
+// the run's atomics: one per run and sum instead of one per particle.  The
+// offset sums are integers, exact in any order; only the velocity sums'
+// last bits depend on the order (as they do on the atomics').
 constexpr int kPriv = 1024;
 constexpr int kStatsBlock = 256;
+
+// the lane-order neighbours' halo numbers and run boundaries of a wave
+__device__ __forceinline__ bool run_head(int32_t g, int lane)
+{
+    const int32_t gp = __shfl_up(g, 1);
+    return lane == 0 || gp != g;
+}
+
+__device__ __forceinline__ bool run_tail(int32_t g, int lane)
+{
+    const int32_t gn = __shfl_down(g, 1);
+    return lane == 63 || gn != g;
+}
 
 __global__ void __launch_bounds__(kStatsBlock)
 k_stats_sum(int64_t n, const uint32_t *__restrict__ pos, const float *__restrict__ vel,
             const int32_t *__restrict__ group, int32_t n_groups,
             const hop_group_info *__restrict__ groups, int periodic, int64_t G,
-            unsigned long long *__restrict__ osum, double *__restrict__ vsum,
-            uint32_t *__restrict__ dflags)
+            const SortedRec *__restrict__ order, unsigned long long *__restrict__ osum,
+            double *__restrict__ vsum, uint32_t *__restrict__ dflags)
 {
     __shared__ unsigned long long lo[kPriv * 3];
     __shared__ double lv[kPriv * 3];
@@ -48,29 +71,69 @@ k_stats_sum(int64_t n, const uint32_t *__restrict__ pos, const float *__restrict
         lv[t] = 0.0;
     }
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t g = group[i];
-        if (g < 0) continue;
-        if (g >= n_groups) {
-            atomicOr(dflags, DERR_INDEX);
-            continue;
-        }
-        const int32_t pk = groups[g].peak;
-        if (pk < 0 || pk >= n) {
-            atomicOr(dflags, DERR_INDEX);
-            continue;
-        }
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t base = wave * 64; base < n; base += n_waves * 64) {
+        const int64_t t = base + lane;
+        int32_t g = -1;
+        long long d[3] = {0, 0, 0};
+        double v[3] = {0.0, 0.0, 0.0};
+        const int64_t i = t < n ? (order ? (int64_t)order[t].j : t) : -1;
+        if (t < n && (i < 0 || i >= n)) atomicOr(dflags, DERR_INDEX);
+        if (i >= 0 && i < n) {
+            g = group[i];
+            if (g >= n_groups) {
+                atomicOr(dflags, DERR_INDEX);
+                g = -1;
+            } else if (g >= 0) {
+                const int32_t pk = groups[g].peak;
+                if (pk < 0 || pk >= n) {
+                    atomicOr(dflags, DERR_INDEX);
+                    g = -1;
+                } else {
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            const int64_t d = min_image((int64_t)pos[3 * i + k] - (int64_t)pos[3 * (int64_t)pk + k], periodic, G);
-            const double v = vel ? (double)vel[3 * i + k] : 0.0;
-            if (g < kPriv) {
-                atomicAdd(&lo[3 * g + k], (unsigned long long)d);  // two's complement sum
-                if (vel) atomicAdd(&lv[3 * g + k], v);
-            } else {
-                atomicAdd(&osum[3 * (int64_t)g + k], (unsigned long long)d);
-                if (vel) atomicAdd(&vsum[3 * (int64_t)g + k], v);
+                    for (int k = 0; k < 3; k++) {
+                        d[k] = min_image((int64_t)pos[3 * i + k] - (int64_t)pos[3 * (int64_t)pk + k],
+                                         periodic, G);
+                        if (vel) v[k] = (double)vel[3 * i + k];
+                    }
+                }
+            }
+        }
+        // segmented inclusive sums over the runs of equal g: a lane adds the
+        // partial sum `off` lanes below until its range reaches its run's head
+        bool f = run_head(g, lane);
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            long long du[3];
+            double vu[3];
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                du[k] = __shfl_up(d[k], off);
+                vu[k] = vel ? __shfl_up(v[k], off) : 0.0;
+            }
+            const bool fu = __shfl_up((int)f, off) != 0;
+            if (lane >= off && !f) {
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    d[k] += du[k];
+                    v[k] = vu[k] + v[k];
+                }
+                f = fu;
+            }
+        }
+        const bool tail = run_tail(g, lane);  // (every lane takes part in the shuffle)
+        if (g >= 0 && tail) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                if (g < kPriv) {
+                    atomicAdd(&lo[3 * g + k], (unsigned long long)d[k]);  // two's complement sum
+                    if (vel) atomicAdd(&lv[3 * g + k], v[k]);
+                } else {
+                    atomicAdd(&osum[3 * (int64_t)g + k], (unsigned long long)d[k]);
+                    if (vel) atomicAdd(&vsum[3 * (int64_t)g + k], v[k]);
+                }
             }
         }
     }
@@ -114,32 +177,57 @@ __global__ void k_stats_halo(int64_t n, int32_t n_groups, const uint32_t *__rest
     }
 }
 
+// Maximum radius per halo: the same particle order and the same per-run
+// reduction (a maximum, exact in any order) as k_stats_sum.
 __global__ void __launch_bounds__(kStatsBlock)
 k_stats_radius(int64_t n, const uint32_t *__restrict__ pos, const int32_t *__restrict__ group,
                int32_t n_groups, const hop_group_info *__restrict__ groups, int periodic,
-               int64_t G, const double *__restrict__ mean,
+               int64_t G, const SortedRec *__restrict__ order, const double *__restrict__ mean,
                unsigned long long *__restrict__ rmax_bits)
 {
     __shared__ unsigned long long lr[kPriv];
     for (int t = threadIdx.x; t < kPriv; t += kStatsBlock) lr[t] = 0ull;
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t g = group[i];
-        if (g < 0 || g >= n_groups) continue;
-        const int64_t pk = groups[g].peak;
-        if (pk < 0 || pk >= n) continue;
-        double e[3];
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t base = wave * 64; base < n; base += n_waves * 64) {
+        const int64_t t = base + lane;
+        int32_t g = -1;
+        unsigned long long rb = 0ull;
+        const int64_t i = t < n ? (order ? (int64_t)order[t].j : t) : -1;
+        if (i >= 0 && i < n) {  // (an index outside is reported by k_stats_sum)
+            g = group[i];
+            const int64_t pk = (g >= 0 && g < n_groups) ? (int64_t)groups[g].peak : -1;
+            if (pk < 0 || pk >= n) {
+                g = -1;  // reported by k_stats_sum
+            } else {
+                double e[3];
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            const int64_t d = min_image((int64_t)pos[3 * i + k] - (int64_t)pos[3 * pk + k], periodic, G);
-            e[k] = (double)d - mean[3 * (int64_t)g + k];
+                for (int k = 0; k < 3; k++) {
+                    const int64_t d = min_image((int64_t)pos[3 * i + k] - (int64_t)pos[3 * pk + k], periodic, G);
+                    e[k] = (double)d - mean[3 * (int64_t)g + k];
+                }
+                const double r = __builtin_sqrt((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]);
+                // non-negative doubles order like their bit patterns
+                rb = (unsigned long long)__double_as_longlong(r);
+            }
         }
-        const double r = __builtin_sqrt((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]);
-        // non-negative doubles order like their bit patterns
-        const unsigned long long rb = (unsigned long long)__double_as_longlong(r);
-        if (g < kPriv) atomicMax(&lr[g], rb);
-        else atomicMax(&rmax_bits[g], rb);
+        bool f = run_head(g, lane);
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned long long ru = __shfl_up(rb, off);
+            const bool fu = __shfl_up((int)f, off) != 0;
+            if (lane >= off && !f) {
+                rb = ru > rb ? ru : rb;
+                f = fu;
+            }
+        }
+        const bool tail = run_tail(g, lane);  // (every lane takes part in the shuffle)
+        if (g >= 0 && tail) {
+            if (g < kPriv) atomicMax(&lr[g], rb);
+            else atomicMax(&rmax_bits[g], rb);
+        }
     }
     __syncthreads();
     const int lim = min(n_groups, kPriv);
@@ -185,15 +273,22 @@ int stats_launch(hop_ctx *ctx, int64_t n, const uint32_t *pos, const float *vel,
     k_zero_u64<<<hop_grid(2 * g3, 256), 256, 0, s>>>(osum, 2 * g3);  // osum and vsum are adjacent
     k_zero_u64<<<hop_grid(n_groups, 256), 256, 0, s>>>((unsigned long long *)rmax, n_groups);
     const int grid = (int)std::min<int64_t>(hop_grid(n, kStatsBlock), (int64_t)ctx->n_cu * 8);
-    k_stats_sum<<<grid, kStatsBlock, 0, s>>>(n, pos, vel, group, n_groups, groups, periodic, G, osum,
-                                                 vel ? vsum : nullptr, (uint32_t *)ctx->flags.ptr);
+    // Morton order when the context's last kNN call sorted n particles (any
+    // permutation gives the same offsets and radii; an index outside [0, n),
+    // which only a sorted copy left incomplete by a failed call could hold,
+    // is reported like a bad group number)
+    const SortedRec *order = (ctx->perm_n == n && ctx->recs.bytes >= (size_t)n * sizeof(SortedRec))
+                                 ? (const SortedRec *)ctx->recs.ptr
+                                 : nullptr;
+    k_stats_sum<<<grid, kStatsBlock, 0, s>>>(n, pos, vel, group, n_groups, groups, periodic, G, order,
+                                             osum, vel ? vsum : nullptr, (uint32_t *)ctx->flags.ptr);
     HOPCHK(ctx, hipGetLastError());
     k_stats_halo<<<hop_grid(n_groups, 256), 256, 0, s>>>(n, n_groups, pos, groups, periodic, G, osum,
                                                          vsum, mean, com, vel ? vbulk : nullptr,
                                                          (uint32_t *)ctx->flags.ptr);
     HOPCHK(ctx, hipGetLastError());
-    k_stats_radius<<<grid, kStatsBlock, 0, s>>>(n, pos, group, n_groups, groups, periodic, G, mean,
-                                                    (unsigned long long *)rmax);
+    k_stats_radius<<<grid, kStatsBlock, 0, s>>>(n, pos, group, n_groups, groups, periodic, G, order,
+                                                mean, (unsigned long long *)rmax);
     HOPCHK(ctx, hipGetLastError());
     return HOP_OK;
 }

@@ -35,12 +35,13 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def _check(ctx, p, params, r, label, vel=None):
+def _check(ctx, p, params, r, label, vel=None, stats_ctx=None):
     from oracle import halo
     out = ctx.run(p.pos, params, padded=p.padded)
     assert np.array_equal(_np(out["group"]), r.group), label
-    g = ctx.halo_stats(p.pos, out["group"], out["table"], params, vel=vel)
-    ctx.sync()
+    sc = stats_ctx or ctx
+    g = sc.halo_stats(p.pos, out["group"], out["table"], params, vel=vel)
+    sc.sync()
     ref = halo.halo_stats(p.pos, r.group, r.g_peak, periodic=params.periodic, vel=vel)
     print(f"[halo] {label}: {r.n_groups} halos", flush=True)
     assert np.array_equal(ref["count"], r.g_count)
@@ -70,6 +71,23 @@ def test_config1_with_velocities(ctx, orc):
     r = orc.run(p.pos, mean_density=p.mean_density)
     vel = np.random.default_rng(5).normal(0, 300, (p.n, 3)).astype(np.float32)
     _check(ctx, p, HopParams(mean_density=p.mean_density), r, "config1", vel=vel)
+
+
+def test_input_order_on_a_fresh_context(ctx, orc):
+    """A context whose last kNN call sorted these particles takes the members
+    in that Morton order (the other tests); one that has sorted nothing
+    takes them in input order: the same exact centres and radii, the bulk
+    velocities within the same bound."""
+    from paper_1001_3411_amd import HopContext, HopParams
+    p = synth.config(1)
+    r = orc.run(p.pos, mean_density=p.mean_density)
+    vel = np.random.default_rng(6).normal(0, 300, (p.n, 3)).astype(np.float32)
+    fresh = HopContext(0)
+    try:
+        _check(ctx, p, HopParams(mean_density=p.mean_density), r, "config1-input-order", vel=vel,
+               stats_ctx=fresh)
+    finally:
+        fresh.close()
 
 
 def test_halo_across_the_box_edge(ctx, orc):
