@@ -220,6 +220,17 @@ int hop_sync(hop_ctx *ctx, void *stream)
     return hop_check_device(ctx, (hipStream_t)stream, "hop_sync");
 }
 
+// The kNN call; a failed one may leave the sorted copy incomplete, so its
+// order is then not offered to later stages (ctx->perm_n = 0).
+static int density_call(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
+                        const hop_params *p, double *density, int32_t *nbr, int32_t *nbr16s,
+                        double *dens_s, hipStream_t s)
+{
+    const int rc = hop_density_impl(ctx, n, pos, id, p, density, nbr, nbr16s, dens_s, s);
+    if (rc != HOP_OK) ctx->perm_n = 0;
+    return rc;
+}
+
 int hop_density(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
                 const hop_params *p, double *density, int32_t *nbr, void *stream)
 {
@@ -228,7 +239,7 @@ int hop_density(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
     HOPTRY(hop_check_params(ctx, n, p));
     if (!pos || !density) return hop_fail(ctx, HOP_ERR_ARG, "pos and density must be non-NULL");
     HOPTRY(hop_set_device(ctx));
-    return hop_density_impl(ctx, n, pos, id, p, density, nbr, nullptr, nullptr, (hipStream_t)stream);
+    return density_call(ctx, n, pos, id, p, density, nbr, nullptr, nullptr, (hipStream_t)stream);
 }
 
 int hop_density_link(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t *id,
@@ -244,7 +255,7 @@ int hop_density_link(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     if (p->n_hop > 16) {
         // no sorted copy for longer link lists: the two calls as they are
         if (!nbr) return hop_fail(ctx, HOP_ERR_ARG, "nbr must be non-NULL when n_hop > 16");
-        HOPTRY(hop_density_impl(ctx, n, pos, id, p, density, nbr, nullptr, nullptr, s));
+        HOPTRY(density_call(ctx, n, pos, id, p, density, nbr, nullptr, nullptr, s));
         const int32_t *tk = id ? (const int32_t *)ctx->tk.ptr : nullptr;
         return hop_link_impl(ctx, n, nbr, density, tk, padded, p, hop, s);
     }
@@ -253,7 +264,7 @@ int hop_density_link(hop_ctx *ctx, int64_t n, const uint32_t *pos, const int64_t
     HOPTRY(hop_reserve(ctx, ctx->srt_dens, rows * 8));
     int32_t *nbr16s = (int32_t *)ctx->srt_nbr.ptr;
     double *dens_s = (double *)ctx->srt_dens.ptr;
-    HOPTRY(hop_density_impl(ctx, n, pos, id, p, density, nbr, nbr16s, dens_s, s));
+    HOPTRY(density_call(ctx, n, pos, id, p, density, nbr, nbr16s, dens_s, s));
     const int32_t *tk = id ? (const int32_t *)ctx->tk.ptr : nullptr;
     return hop_link_sorted_impl(ctx, n, nbr16s, dens_s, density, tk, padded, p, hop, s);
 }
