@@ -135,6 +135,25 @@ def test_bounded_search_is_exact(ctx, orc, box1):
     ctx.radius_load(0)
 
 
+@pytest.mark.parametrize("waves", [8, 37])
+def test_bounded_search_with_few_persistent_waves(ctx, orc, box1, waves):
+    """The one-box kNN launch is persistent: each wave takes many buckets in
+    turn.  The bounded search records its misses per bucket and the fallback
+    pass searches those lanes again; with few waves the results are still
+    the oracle's."""
+    from paper_1001_3411_amd import HOP_RADIUS_ANALYTIC
+    from paper_1001_3411_amd.radius import calibrate
+    p, prm, cb, nbr, feats, target = box1
+    calibrate(ctx, None, feats, target, miss_rate=0.05, kind=HOP_RADIUS_ANALYTIC)
+    ctx.set_tuning(persistent_waves=waves)
+    try:
+        st = _exact_with(ctx, orc, p, prm, f"analytic, {waves} waves")
+        assert st["misses"] > 0 and st["redo_buckets"] > 0
+    finally:
+        ctx.set_tuning(persistent_waves=0)
+        ctx.radius_load(0)
+
+
 def test_search_modes_on_the_clustered_box(ctx):
     """The 16.8M-particle Zel'dovich box under the plain search, the analytic
     radius and the trained network (each calibrated for a 1% miss rate):
